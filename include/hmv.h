@@ -1,0 +1,149 @@
+/* hmv.h -- exact multiprecision Hankel / Toeplitz / circulant matrix-vector
+ * products on AMD MI355X (gfx950).  C ABI of libhmv.so.
+ *
+ * Problem statement (Beliakov, "On fast matrix-vector multiplication with a
+ * Hankel matrix in multiprecision arithmetics", Section 4, Algorithm 1 input
+ * and output): given n, a vector a of 2n-1 entries that defines the Hankel
+ * matrix A_H[i][j] = a_{i+j-1} (Section 2, eq. (1)) and x of n entries,
+ * compute y = A_H x.  The Toeplitz matrix of eq. (2), A_T[i][j] = a_{n-i+j},
+ * uses the same 2n-1 entries; the circulant of eq. (3) is given by its first
+ * column of n entries, A_C[i][j] = c_{((i-j) mod n)+1}.
+ *
+ * NUMBER FORMAT.  Every number is fixed point with P fractional bits: value
+ * X * 2^-P, X an integer.  It is stored as W = hmv_words(P) = ceil((P+64)/64)
+ * little-endian uint64 words holding X in two's complement; an array of
+ * numbers is row-major [count][W].  Inputs must satisfy |value| <= 1
+ * (|X| <= 2^P).  Each output y_i is the exact sum rounded once to the nearest
+ * multiple of 2^-P, ties to even; |y_i| <= n fits in W words.  The result is
+ * unique, so every algorithm below returns identical words.
+ *
+ * MEMORY.  Every array argument (h, x, y, workspaces, plan memory) is a
+ * DEVICE pointer owned by the caller; the library never allocates device
+ * memory.  Sizes come from the *_bytes queries.  y must not alias h, x or a
+ * workspace.  Work is enqueued on `stream` (a hipStream_t; NULL = the null
+ * stream); outputs are valid once the stream has synchronised.
+ *
+ * ERRORS.  Calls return an hmv_status code and never throw.  Argument errors
+ * (n < 1, P outside [1, HMV_MAX_P], null pointers, short buffers, unknown
+ * kind or algorithm) are reported synchronously as HMV_EINVAL.  Inputs with
+ * |value| > 1 are detected on the device: the call still completes (with
+ * unspecified y) and hmv_read_status() on its workspace returns HMV_ERANGE.
+ */
+#ifndef HMV_H
+#define HMV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HMV_MAX_P 40960
+#define HMV_MAX_N 16384
+
+typedef enum {
+  HMV_OK = 0,
+  HMV_EINVAL = -1,       /* bad argument                                        */
+  HMV_ERANGE = -2,       /* an input had |value| > 1 (device-detected)          */
+  HMV_ENOMEM = -3,       /* a caller buffer is too small                        */
+  HMV_EDEVICE = -4,      /* a HIP runtime call failed                           */
+  HMV_EBOUND = -5,       /* no exact path: the FP64 bound fails and NTT is off  */
+  HMV_EUNSUPPORTED = -6  /* size outside what the chosen algorithm handles      */
+} hmv_status;
+
+typedef enum { HMV_HANKEL = 0, HMV_TOEPLITZ = 1, HMV_CIRCULANT = 2 } hmv_kind;
+
+typedef enum {
+  HMV_AUTO = 0,        /* split-FFT when its proven bound holds, else NTT          */
+  HMV_SPLIT_FFT = 1,   /* limbs + 2-D binary64 FFT correlation (Section 3)         */
+  HMV_NTT = 2,         /* limbs + 2-D number-theoretic transform mod 2^64-2^32+1   */
+  HMV_KARATSUBA = 3,   /* Algorithm 1 of Section 4 over the index axis             */
+  HMV_SCHOOLBOOK = 4   /* the plain O(n^2) sum of Section 2, exact on limbs        */
+} hmv_algo;
+
+/* Words per number: ceil((P+64)/64), or HMV_EINVAL if P is out of range. */
+int64_t hmv_words(int32_t P);
+
+/* Text for a status code (static storage). */
+const char* hmv_strerror(int code);
+
+/* Name and text of the last HIP runtime error seen by this thread (behind an
+ * HMV_EDEVICE return); empty if none.  Thread-local static storage. */
+const char* hmv_last_error(void);
+
+/* ---------------------------------------------------------------- one-shot
+ * y = A x for one matrix, with no state kept between calls.  h has 2n-1
+ * numbers (Hankel, Toeplitz) or n numbers (circulant); x and y have n.
+ * ws must hold hmv_oneshot_workspace_bytes(kind, n, P, algo) bytes; its
+ * first 256 bytes receive the device status of this call (hmv_read_status).
+ * With algo SPLIT_FFT or AUTO the call synchronises `stream` once, to read
+ * the limb norms that fix the limb width (the error bound needs them).     */
+int64_t hmv_oneshot_workspace_bytes(int kind, int64_t n, int32_t P, int algo);
+int hmv_hankel_matvec(const uint64_t* h, const uint64_t* x, uint64_t* y, int64_t n, int32_t P,
+                      int algo, void* ws, int64_t ws_bytes, void* stream);
+int hmv_toeplitz_matvec(const uint64_t* h, const uint64_t* x, uint64_t* y, int64_t n, int32_t P,
+                        int algo, void* ws, int64_t ws_bytes, void* stream);
+int hmv_circulant_matvec(const uint64_t* c, const uint64_t* x, uint64_t* y, int64_t n,
+                         int32_t P, int algo, void* ws, int64_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- plans
+ * plan_h keeps the 2-D transform of h resident in caller memory so that a
+ * session of matvecs with one fixed matrix (the repeated products of a
+ * Lanczos iteration, Section 1) pays for it once.
+ *
+ * hmv_plan_bytes / hmv_workspace_bytes give sizes that hold for every limb
+ * width the planner may pick (the width depends on the data of h through
+ * the error bound).  plan_mem must stay valid and unmodified while the plan
+ * is used; ws is scratch for plan_h and for each plan_matvec, and its first
+ * 256 bytes receive the device status of that call.  hmv_plan_h synchronises
+ * `stream` once (limb norms); hmv_plan_matvec is fully asynchronous.  A plan
+ * is immutable: several streams may use it at once, each with its own ws.
+ * The handle is host memory; hmv_plan_destroy frees only the handle.      */
+typedef struct hmv_plan hmv_plan;
+
+typedef struct {
+  int32_t kind, algo;     /* algo actually used                                 */
+  int64_t n;
+  int32_t P, w, L;        /* limb width and limbs per number                     */
+  int64_t Nt, Nz;         /* FFT / NTT sizes on the index and limb axes          */
+  double bound;           /* proven bound on |coefficient error| (FP64 path)     */
+  double beta;            /* bound on the error of the tabulated roots           */
+  double norm_h;          /* Euclidean norm of the limb digits of h              */
+  int64_t plan_bytes;     /* plan memory actually used                           */
+  int64_t matvec_workspace_bytes;
+} hmv_plan_info_t;
+
+int64_t hmv_plan_bytes(int kind, int64_t n, int32_t P, int algo);
+int64_t hmv_workspace_bytes(int kind, int64_t n, int32_t P, int algo);
+int hmv_plan_h(hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P, int algo,
+               void* plan_mem, int64_t plan_bytes, void* ws, int64_t ws_bytes, void* stream);
+int hmv_plan_matvec(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* ws,
+                    int64_t ws_bytes, void* stream);
+int64_t hmv_plan_workspace_bytes(const hmv_plan* plan);
+int hmv_plan_info(const hmv_plan* plan, hmv_plan_info_t* info);
+int hmv_plan_destroy(hmv_plan* plan);
+
+/* ---------------------------------------------------------------- diagnostics
+ * Host-only helpers (no device access).
+ * hmv_fft_error_bound: the bound used to pick the limb width of the binary64
+ *   path, ||a||_2 ||b||_2 ((1+e)^(3k) (1+e sqrt5)^(3k+1) (1+beta)^(3k) - 1),
+ *   e = 2^-53, k = log2_points (the form of Percival's bound for FFT
+ *   multiplication, Math. Comp. 72 (2003)).
+ * hmv_twiddle_beta: the beta of the library's root tables.
+ * hmv_debug_force_width: tests only; restrict the binary64 limb width to w
+ *   (0 restores the search).  The bound is still enforced.                  */
+double hmv_fft_error_bound(double norm_h, double norm_x, int32_t log2_points, double beta);
+double hmv_twiddle_beta(void);
+int hmv_debug_force_width(int32_t w);
+
+/* Device status of the last call that used workspace `ws`: synchronises
+ * `stream`, stores the ST flags (bit 0 range, bit 1 bound, bit 2 spin limit)
+ * and, for the split-FFT path, the largest distance of an FFT output
+ * coefficient from its nearest integer.  Either out pointer may be NULL.
+ * Returns HMV_ERANGE if an input was out of range, else HMV_OK.            */
+int hmv_read_status(const void* ws, void* stream, int32_t* flags, double* max_round_err);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMV_H */

@@ -1,0 +1,185 @@
+// Binary64 complex FFT engine for one work-group, data resident in LDS.
+//
+// Transform: X[f] = sum_t x[t] exp(sign * 2 pi i t f / N), sign = -1 forward,
+// +1 inverse (unnormalised).  Stockham autosort passes: radix 16 while at
+// least 16 points remain, then one tail pass of radix 2, 4 or 8.  A pass of
+// radix R with span Ns (the product of the earlier radices) reads element
+// b + r N/R, multiplies it by the tabulated root exp(sign 2 pi i r k / (R Ns))
+// with k = b mod Ns, runs an R-point DFT and writes element
+// (b - k) R + k + r Ns.  The output comes out in natural order.
+//
+// Radix-16 DFTs are two radix-4 stages with one internal twiddle; radix-4
+// uses only +-1 and +-i.  Along every data path each binary stage therefore
+// carries at most one inexact multiplication by a tabulated or constant root,
+// which is the operation model of the error bound used to pick the limb width.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_layout.h"
+
+namespace hmv {
+
+
+// The tables live in the code object of the one translation unit that
+// includes this header (the split-FFT kernels); the host fills them once per
+// device with hipMemcpyToSymbol.
+__device__ double2 g_tw[kTwEntries];
+__device__ double2 g_rtw[kRealTwEntries];
+
+// ---------------------------------------------------------------- complex ops
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
+// multiply by sign*i  (sign = +-1): exact
+__device__ __forceinline__ double2 mul_si(double2 a, int sign) {
+  return sign > 0 ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// 4-point DFT in place
+__device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3, int sign) {
+  const double2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  const double2 t2 = cadd(a1, a3), t3 = mul_si(csub(a1, a3), sign);
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+// cos / sin of 2 pi m / 16 for m = 1, 2, 3 (correctly rounded constants)
+constexpr double kC16_1 = 0.92387953251128673848;   // cos(pi/8)
+constexpr double kS16_1 = 0.38268343236508978178;   // sin(pi/8)
+constexpr double kC16_2 = 0.70710678118654757274;   // cos(pi/4)
+
+// multiply by exp(sign * 2 pi i m / 16) for m in 0..9 used by the radix-16 split
+__device__ __forceinline__ double2 rot16(double2 a, int m, int sign) {
+  double c, s;
+  switch (m) {
+    case 0: return a;
+    case 1: c = kC16_1; s = kS16_1; break;
+    case 2: c = kC16_2; s = kC16_2; break;
+    case 3: c = kS16_1; s = kC16_1; break;
+    case 4: return mul_si(a, sign);
+    case 6: c = -kC16_2; s = kC16_2; break;
+    case 9: c = -kC16_1; s = -kS16_1; break;
+    default: c = 1.0; s = 0.0; break;
+  }
+  s = sign > 0 ? s : -s;
+  return make_double2(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+template <int R>
+__device__ __forceinline__ void dft(double2* v, int sign);
+
+template <>
+__device__ __forceinline__ void dft<2>(double2* v, int) {
+  const double2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <>
+__device__ __forceinline__ void dft<4>(double2* v, int sign) {
+  dft4(v[0], v[1], v[2], v[3], sign);
+}
+
+template <>
+__device__ __forceinline__ void dft<8>(double2* v, int sign) {
+  double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3, sign);
+  dft4(o0, o1, o2, o3, sign);
+  // exp(sign 2 pi i k / 8), k = 0..3
+  o1 = rot16(o1, 2, sign);
+  o2 = mul_si(o2, sign);
+  o3 = rot16(o3, 6, sign);
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+template <>
+__device__ __forceinline__ void dft<16>(double2* v, int sign) {
+  // X[k1 + 4 k2] = sum_n2 w16^(n2 k1) w4^(n2 k2) DFT4_n1(v[n2 + 4 n1])[k1]
+  double2 u[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    double2 a0 = v[n2], a1 = v[n2 + 4], a2 = v[n2 + 8], a3 = v[n2 + 12];
+    dft4(a0, a1, a2, a3, sign);
+    u[n2][0] = a0;
+    u[n2][1] = rot16(a1, n2, sign);
+    u[n2][2] = rot16(a2, 2 * n2, sign);
+    u[n2][3] = rot16(a3, 3 * n2, sign);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    double2 a0 = u[0][k1], a1 = u[1][k1], a2 = u[2][k1], a3 = u[3][k1];
+    dft4(a0, a1, a2, a3, sign);
+    v[k1] = a0;
+    v[k1 + 4] = a1;
+    v[k1 + 8] = a2;
+    v[k1 + 12] = a3;
+  }
+}
+
+// One Stockham pass over N points held in buf (LDS).  Requires
+// blockDim.x * NB >= N / R.  Ends with a barrier.
+template <int R, int NB>
+__device__ __forceinline__ void stockham_pass(double2* buf, int N, int Ns, int sign) {
+  const int nbf = N / R;
+  const int T = blockDim.x;
+  const double2* tw = g_tw + tw_offset(R, Ns);
+  double2 v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = threadIdx.x + i * T;
+    if (b < nbf) {
+      const int k = b & (Ns - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[b + r * nbf];
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          double2 w = tw[k * (R - 1) + (r - 1)];
+          if (sign > 0) w.y = -w.y;
+          v[i][r] = cmul(v[i][r], w);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = threadIdx.x + i * T;
+    if (b < nbf) {
+      const int k = b & (Ns - 1);
+      dft<R>(v[i], sign);
+      const int base = (b - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform of N = 2^logN points (2 <= N <= 8192) in buf.  Requires
+// blockDim.x >= N / 16 (blockDim.x >= 1 for N < 16).  Caller must have
+// synchronised after filling buf; ends with a barrier.
+__device__ __forceinline__ void fft_lds(double2* buf, int logN, int sign) {
+  const int N = 1 << logN;
+  int Ns = 1;
+  const int a = logN >> 2, rem = logN & 3;
+  for (int p = 0; p < a; ++p) {
+    stockham_pass<16, 1>(buf, N, Ns, sign);
+    Ns <<= 4;
+  }
+  if (rem == 1) stockham_pass<2, 8>(buf, N, Ns, sign);
+  else if (rem == 2) stockham_pass<4, 4>(buf, N, Ns, sign);
+  else if (rem == 3) stockham_pass<8, 2>(buf, N, Ns, sign);
+}
+
+}  // namespace hmv

@@ -1,0 +1,45 @@
+// Internal launcher declarations shared by the HIP translation units and the
+// C-ABI layer.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hmv {
+
+struct DevStatus;
+
+constexpr int kMaxWords = 648;      // W for P up to 40960 is 641
+constexpr int kSchoolMaxK = 16;     // coefficients per thread in the schoolbook row kernel
+
+// status block
+hipError_t launch_clear_status(DevStatus* st, hipStream_t s);
+
+// schoolbook path
+size_t school_lds_bytes(int L, int w, int P, int W);
+hipError_t launch_split_digits_f64(const uint64_t* in, int W, int P, int w, int L, int count,
+                                   int gather_n, double* out, int ld, DevStatus* st,
+                                   hipStream_t s);
+hipError_t launch_school_rows(const double* hd, const double* xd, int n, int L, int ld, int w,
+                              int P, int W, int out_reverse, uint64_t* y, hipStream_t s);
+
+}  // namespace hmv
+
+namespace hmv {
+
+// split-FFT path
+double fft_twiddle_beta();
+hipError_t fft_tables_init();
+hipError_t launch_h_norms(const uint64_t* h, int W, int P, int rows, int gather_n, int wlo,
+                          int whi, unsigned long long* norms, DevStatus* st, hipStream_t s);
+hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int count,
+                           int gather_n, int logM, double2* out, int rows_alloc, DevStatus* st,
+                           hipStream_t s);
+hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, double scale,
+                            double2* Hh, hipStream_t s);
+hipError_t launch_cols_pass(const double2* X1, const double2* Hh, int n, int C, int logNt,
+                            double2* Y1, hipStream_t s);
+hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
+                           int out_reverse, uint64_t* y, DevStatus* st, hipStream_t s);
+
+}  // namespace hmv

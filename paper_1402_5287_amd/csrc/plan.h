@@ -1,0 +1,67 @@
+// Host-side helpers shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hmv {
+
+constexpr int64_t kAlign = 256;
+constexpr int64_t kStatusBytes = 256;
+
+int64_t align_up(int64_t v);
+
+// Sequential carving of a caller-owned buffer.  With base == nullptr it only
+// measures.
+struct Carver {
+  char* base;
+  int64_t off;
+  int64_t cap;
+  bool ok;
+  void* take(int64_t bytes);
+};
+
+bool valid_kind(int kind);
+int64_t words_of(int32_t P);
+int limbs_of(int32_t P, int w);
+int school_width(int64_t n, int32_t P);
+int status_from_hip(hipError_t e, const char* where);
+void clear_stale_error();
+
+// ------------------------------------------------------------------ plans
+constexpr int kFftWMin = 8;        // candidate limb widths of the binary64 path
+constexpr int kFftWMax = 20;
+constexpr int kFftMaxLogNz = 13;   // limb-axis real FFT up to 8192 points (LDS)
+constexpr int kFftMaxLogNt = 13;   // index-axis FFT up to 8192 points (LDS)
+constexpr int kNormSlots = 32;
+
+extern int g_force_w;              // tests: restrict the width candidates to one value
+
+struct FftSizes {
+  int w, L, logM, logNt, C, tiles;
+  int64_t Nt, Nz;
+  int64_t plan_bytes, plan_scratch, mv_scratch;
+};
+
+int ilog2_ceil(int64_t v);
+bool fft_sizes(int64_t n, int32_t P, int w, FftSizes* z);
+bool fft_worst_sizes(int64_t n, int32_t P, FftSizes* z);
+
+// planned paths (split-FFT, NTT, Karatsuba) used by the one-shot entry points
+int64_t oneshot_planned_bytes(int kind, int64_t n, int32_t P, int algo);
+int oneshot_planned(int kind, const uint64_t* h, const uint64_t* x, uint64_t* y, int64_t n,
+                    int32_t P, int algo, void* ws, int64_t ws_bytes, hipStream_t s);
+
+}  // namespace hmv
+
+// opaque plan handle of the C ABI (host memory only)
+struct hmv_plan {
+  int kind = 0, algo = 0;
+  int64_t n = 0;
+  int32_t P = 0;
+  int device = 0;
+  int w = 0, L = 0, logM = 0, logNt = 0, C = 0, tiles = 0;
+  int64_t Nt = 0, Nz = 0;
+  double bound = 0.0, beta = 0.0, norm_h = 0.0;
+  int64_t plan_bytes_used = 0, mv_scratch = 0;
+  double2* Hh = nullptr;           // resident spectrum of h (in caller plan memory)
+};

@@ -1,0 +1,25 @@
+// Host generation of the binary64 root-of-unity tables and the rigorous
+// error bound that fixes the limb width.
+#pragma once
+#include <stdint.h>
+
+namespace hmv {
+
+// exp(-2 pi i m / N), N a power of two, computed in long double with an
+// octant reduction and rounded to binary64.
+void unit_root(int64_t m, int64_t N, double* re, double* im);
+
+// Fill the Stockham table (2 * kTwEntries doubles) and the real-packing
+// table (2 * kRealTwEntries doubles).  Returns the largest |table - root|
+// observed against the long double values, plus a margin for the long double
+// evaluation itself: the beta of the error bound.
+double gen_fft_tables(double* tw, double* rtw);
+
+// Percival-type bound on the max-norm error of a binary64 FFT convolution
+// z = IFFT(FFT(a) . FFT(b)) with transforms of 2^k points:
+//   ||a||_2 ||b||_2 ((1+eps)^(3k) (1+eps sqrt5)^(3k+1) (1+beta)^(3k) - 1),
+// eps = 2^-53, evaluated through log1p / expm1 in long double so that terms
+// like 1 + 2^-53 are not lost.
+double fft_conv_bound(double norm_a, double norm_b, int k, double beta);
+
+}  // namespace hmv

@@ -1,0 +1,135 @@
+"""Thin ctypes binding of libhmv (include/hmv.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device buffers are torch CUDA tensors (uint64 words are carried in
+int64 tensors, same bits); the stream is torch's current stream unless one
+is given.  Loading fails loudly when libhmv.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhmv.so")
+
+HANKEL, TOEPLITZ, CIRCULANT = 0, 1, 2
+KINDS = {"hankel": HANKEL, "toeplitz": TOEPLITZ, "circulant": CIRCULANT}
+AUTO, SPLIT_FFT, NTT, KARATSUBA, SCHOOLBOOK = 0, 1, 2, 3, 4
+ALGOS = {"auto": AUTO, "split_fft": SPLIT_FFT, "ntt": NTT, "karatsuba": KARATSUBA,
+         "schoolbook": SCHOOLBOOK}
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EBOUND, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+_c_i64, _c_i32, _c_int, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p
+
+# name -> (restype, argtypes); mirrors include/hmv.h
+SIGNATURES = {
+    "hmv_words": (_c_i64, [_c_i32]),
+    "hmv_strerror": (ctypes.c_char_p, [_c_int]),
+    "hmv_last_error": (ctypes.c_char_p, []),
+    "hmv_oneshot_workspace_bytes": (_c_i64, [_c_int, _c_i64, _c_i32, _c_int]),
+    "hmv_hankel_matvec": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i32, _c_int, _vp, _c_i64, _vp]),
+    "hmv_toeplitz_matvec": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i32, _c_int, _vp, _c_i64, _vp]),
+    "hmv_circulant_matvec": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i32, _c_int, _vp, _c_i64, _vp]),
+    "hmv_read_status": (_c_int, [_vp, _vp, ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+class HmvError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = lib().hmv_strerror(code).decode() if _lib is not None else str(code)
+        if code == EDEVICE and _lib is not None:
+            msg += " [" + lib().hmv_last_error().decode() + "]"
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+def lib():
+    """Load libhmv.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libhmv.so not built at {LIB_PATH}; run "
+                              "`python -m paper_1402_5287_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int, what: str = "") -> int:
+    if code != OK:
+        raise HmvError(code, what)
+    return code
+
+
+def words(P: int) -> int:
+    w = lib().hmv_words(P)
+    if w < 0:
+        raise HmvError(int(w), "hmv_words")
+    return int(w)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def to_device(words_np: np.ndarray, device="cuda"):
+    """uint64 numpy words -> int64 CUDA tensor with the same bits."""
+    import torch
+    a = np.ascontiguousarray(words_np, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+def to_host(t) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def workspace(nbytes: int, device="cuda"):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def oneshot_workspace_bytes(kind, n: int, P: int, algo="auto") -> int:
+    k = KINDS.get(kind, kind)
+    a = ALGOS.get(algo, algo)
+    b = lib().hmv_oneshot_workspace_bytes(k, n, P, a)
+    if b < 0:
+        raise HmvError(int(b), "hmv_oneshot_workspace_bytes")
+    return int(b)
+
+
+def matvec(kind, h, x, y, n: int, P: int, algo="auto", ws=None, stream=None, check=True) -> int:
+    """One-shot y = A x on device tensors.  Returns the status code."""
+    k = KINDS.get(kind, kind)
+    a = ALGOS.get(algo, algo)
+    if ws is None:
+        ws = workspace(oneshot_workspace_bytes(k, n, P, a), device=y.device)
+    fn = {HANKEL: lib().hmv_hankel_matvec, TOEPLITZ: lib().hmv_toeplitz_matvec,
+          CIRCULANT: lib().hmv_circulant_matvec}[k]
+    rc = fn(_ptr(h), _ptr(x), _ptr(y), n, P, a, _ptr(ws), ws.numel(), _stream(stream))
+    if check:
+        _check(rc, "matvec")
+    return rc
+
+
+def read_status(ws, stream=None):
+    """(status, flags, max_round_err) of the last call that used ws."""
+    fl = _c_i32(0)
+    err = ctypes.c_double(0.0)
+    rc = lib().hmv_read_status(_ptr(ws), _stream(stream), ctypes.byref(fl), ctypes.byref(err))
+    return rc, int(fl.value), float(err.value)

@@ -1,0 +1,88 @@
+"""GPU schoolbook path (the plain sum of Section 2) against the oracle,
+bit-exact, through the C ABI."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import fixedpoint as fp, hankel
+from tests.gpu_util import announce, need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(kind, h, x, n, P, algo="schoolbook"):
+    from paper_1402_5287_amd import hmv
+    hd, xd = hmv.to_device(h), hmv.to_device(x)
+    y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+    ws = hmv.workspace(hmv.oneshot_workspace_bytes(kind, n, P, algo))
+    hmv.matvec(kind, hd, xd, y, n, P, algo=algo, ws=ws)
+    rc, flags, _ = hmv.read_status(ws)
+    return hmv.to_host(y), rc, flags
+
+
+@pytest.mark.parametrize("kind", ["hankel", "toeplitz", "circulant"])
+def test_plain_n64_p3322(kind):
+    need_gpu()
+    n, P = 64, 3322
+    h, x = si.plain_case(n, P, seed=0)
+    if kind == "circulant":
+        h = h[:n].copy()
+    announce("school", kind, n, P)
+    y, rc, flags = _run(kind, h, x, n, P)
+    assert rc == 0 and flags == 0
+    want = hankel.matvec_words(kind, h, x, P)
+    assert np.array_equal(y, want)
+
+
+@pytest.mark.parametrize("n,P", [(1, 1), (1, 64), (2, 5), (3, 63), (5, 64), (7, 65), (17, 200),
+                                 (33, 1000), (100, 129), (130, 4096)])
+def test_ragged_sizes(n, P):
+    need_gpu()
+    for kind in ("hankel", "toeplitz", "circulant"):
+        hl = n if kind == "circulant" else 2 * n - 1
+        h = si.uniform(hl, P, (50, n, P))
+        x = si.uniform(n, P, (51, n, P))
+        announce("school ragged", kind, n, P)
+        y, rc, flags = _run(kind, h, x, n, P)
+        assert rc == 0 and flags == 0
+        assert np.array_equal(y, hankel.matvec_words(kind, h, x, P)), (kind, n, P)
+
+
+def test_extremes_and_ties():
+    need_gpu()
+    for P in (4, 64, 65, 3322):
+        lim = 1 << P
+        n = 6
+        # all +-1 entries: largest magnitudes, exact integer outputs
+        H = [lim if k % 2 else -lim for k in range(2 * n - 1)]
+        X = [-lim, lim, lim, -lim, lim, lim]
+        announce("school extremes", P)
+        y, rc, _ = _run("hankel", fp.encode(H, P), fp.encode(X, P), n, P)
+        assert rc == 0
+        assert np.array_equal(y, fp.encode(hankel.matvec_ints("hankel", H, X, P), P))
+        # ties: h = k ulp, x = 0.5
+        H = [k - 5 for k in range(2 * 1 - 1 + 10)][:1]
+        for hv in (1, 3, 5, -1, -3, -5, -7):
+            y, rc, _ = _run("hankel", fp.encode([hv], P), fp.encode([1 << (P - 1)], P), 1, P)
+            assert fp.decode(y) == [fp.round_half_even(hv << (P - 1), P)]
+
+
+def test_basis_vectors_bit_exact():
+    need_gpu()
+    n, P = 40, 700
+    h = si.uniform(2 * n - 1, P, (52,))
+    H = fp.decode(h)
+    for k in (0, 13, n - 1):
+        announce("school basis", k)
+        y, rc, _ = _run("hankel", h, si.unit(n, P, k), n, P)
+        assert fp.decode(y) == H[k:k + n]
+
+
+def test_out_of_range_flag():
+    need_gpu()
+    n, P = 4, 100
+    h = si.uniform(2 * n - 1, P, (53,))
+    x = fp.encode([1, 2, (1 << P) + 1, 0], P)
+    announce("school range")
+    _, rc, flags = _run("hankel", h, x, n, P)
+    assert rc == -2 and (flags & 1)
