@@ -34,7 +34,30 @@ SIGNATURES = {
     "hmv_toeplitz_matvec": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i32, _c_int, _vp, _c_i64, _vp]),
     "hmv_circulant_matvec": (_c_int, [_vp, _vp, _vp, _c_i64, _c_i32, _c_int, _vp, _c_i64, _vp]),
     "hmv_read_status": (_c_int, [_vp, _vp, ctypes.POINTER(_c_i32), ctypes.POINTER(ctypes.c_double)]),
+    "hmv_plan_bytes": (_c_i64, [_c_int, _c_i64, _c_i32, _c_int]),
+    "hmv_workspace_bytes": (_c_i64, [_c_int, _c_i64, _c_i32, _c_int]),
+    "hmv_plan_h": (_c_int, [ctypes.POINTER(_vp), _c_int, _vp, _c_i64, _c_i32, _c_int, _vp, _c_i64,
+                            _vp, _c_i64, _vp]),
+    "hmv_plan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp]),
+    "hmv_plan_workspace_bytes": (_c_i64, [_vp]),
+    "hmv_plan_info": (_c_int, [_vp, _vp]),
+    "hmv_plan_destroy": (_c_int, [_vp]),
+    "hmv_fft_error_bound": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, _c_i32, ctypes.c_double]),
+    "hmv_twiddle_beta": (ctypes.c_double, []),
+    "hmv_debug_force_width": (_c_int, [_c_i32]),
 }
+
+
+class PlanInfo(ctypes.Structure):
+    """Mirror of hmv_plan_info_t."""
+    _fields_ = [("kind", ctypes.c_int32), ("algo", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("P", ctypes.c_int32), ("w", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("Nt", ctypes.c_int64), ("Nz", ctypes.c_int64), ("bound", ctypes.c_double),
+                ("beta", ctypes.c_double), ("norm_h", ctypes.c_double),
+                ("plan_bytes", ctypes.c_int64), ("matvec_workspace_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 _lib = None
 
@@ -133,3 +156,62 @@ def read_status(ws, stream=None):
     err = ctypes.c_double(0.0)
     rc = lib().hmv_read_status(_ptr(ws), _stream(stream), ctypes.byref(fl), ctypes.byref(err))
     return rc, int(fl.value), float(err.value)
+
+
+class Plan:
+    """A resident transform of h (hmv_plan_h) plus its own plan memory.
+
+    matvec(x, y) runs the planned product on device tensors; ws is a per-call
+    scratch buffer (reused across calls on one stream)."""
+
+    def __init__(self, kind, h, n: int, P: int, algo="auto", stream=None):
+        import torch
+        self.kind = KINDS.get(kind, kind)
+        self.algo = ALGOS.get(algo, algo)
+        self.n, self.P = int(n), int(P)
+        dev = h.device
+        pb = lib().hmv_plan_bytes(self.kind, n, P, self.algo)
+        wb = lib().hmv_workspace_bytes(self.kind, n, P, self.algo)
+        if pb < 0 or wb < 0:
+            raise HmvError(int(min(pb, wb)), "plan sizes")
+        self.mem = torch.empty(int(pb), dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(int(wb), dtype=torch.uint8, device=dev)
+        handle = ctypes.c_void_p(0)
+        rc = lib().hmv_plan_h(ctypes.byref(handle), self.kind, _ptr(h), n, P, self.algo,
+                              _ptr(self.mem), self.mem.numel(), _ptr(self.ws), self.ws.numel(),
+                              _stream(stream))
+        _check(rc, "plan_h")
+        self.handle = handle
+        self.mv_ws_bytes = int(lib().hmv_plan_workspace_bytes(self.handle))
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(lib().hmv_plan_info(self.handle, ctypes.byref(inf)), "plan_info")
+        return inf.as_dict()
+
+    def new_workspace(self):
+        return workspace(self.mv_ws_bytes, device=self.mem.device)
+
+    def matvec(self, x, y, ws=None, stream=None, check=True) -> int:
+        ws = self.ws if ws is None else ws
+        rc = lib().hmv_plan_matvec(self.handle, _ptr(x), _ptr(y), _ptr(ws), ws.numel(),
+                                   _stream(stream))
+        if check:
+            _check(rc, "plan_matvec")
+        return rc
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hmv_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def force_width(w: int) -> None:
+    """Tests only: restrict the binary64 limb width (0 = search)."""
+    _check(lib().hmv_debug_force_width(w), "force_width")

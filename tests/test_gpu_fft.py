@@ -1,0 +1,139 @@
+"""Split-FFT path (Section 3 decomposition, exact form) on the GPU against
+the oracle: bit-exact at small sizes, sampled rows plus the GMP Kronecker
+full-vector cross-check at the paper-shaped sizes."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import fixedpoint as fp, hankel, kronecker
+from tests.gpu_util import announce, need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _oneshot(kind, h, x, n, P, algo="split_fft"):
+    from paper_1402_5287_amd import hmv
+    y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+    ws = hmv.workspace(hmv.oneshot_workspace_bytes(kind, n, P, algo))
+    hmv.matvec(kind, hmv.to_device(h), hmv.to_device(x), y, n, P, algo=algo, ws=ws)
+    rc, flags, err = hmv.read_status(ws)
+    return hmv.to_host(y), rc, flags, err
+
+
+@pytest.mark.parametrize("kind", ["hankel", "toeplitz", "circulant"])
+def test_plain_n64_p3322(kind):
+    need_gpu()
+    n, P = 64, 3322
+    h, x = si.plain_case(n, P, seed=0)
+    if kind == "circulant":
+        h = h[:n].copy()
+    announce("fft oneshot", kind, n, P)
+    y, rc, flags, err = _oneshot(kind, h, x, n, P)
+    assert rc == 0 and flags == 0
+    assert err < 0.25
+    assert np.array_equal(y, hankel.matvec_words(kind, h, x, P))
+
+
+@pytest.mark.parametrize("n,P", [(1, 1), (1, 100), (2, 5), (3, 63), (5, 64), (7, 65), (17, 200),
+                                 (33, 1000), (100, 129), (130, 4096), (257, 3322)])
+def test_ragged_sizes(n, P):
+    need_gpu()
+    for kind in ("hankel", "toeplitz", "circulant"):
+        hl = n if kind == "circulant" else 2 * n - 1
+        h = si.uniform(hl, P, (60, n, P))
+        x = si.uniform(n, P, (61, n, P))
+        announce("fft ragged", kind, n, P)
+        y, rc, flags, _ = _oneshot(kind, h, x, n, P)
+        assert rc == 0 and flags == 0
+        assert np.array_equal(y, hankel.matvec_words(kind, h, x, P)), (kind, n, P)
+
+
+def test_extremes_basis_ties():
+    need_gpu()
+    for P in (4, 64, 65, 3322):
+        lim = 1 << P
+        n = 6
+        H = [lim if k % 2 else -lim for k in range(2 * n - 1)]
+        X = [-lim, lim, lim, -lim, lim, lim]
+        announce("fft extremes", P)
+        y, rc, _, _ = _oneshot("hankel", fp.encode(H, P), fp.encode(X, P), n, P)
+        assert rc == 0
+        assert np.array_equal(y, fp.encode(hankel.matvec_ints("hankel", H, X, P), P))
+        for hv in (1, 3, 5, -1, -3, -5, -7):
+            y, rc, _, _ = _oneshot("hankel", fp.encode([hv], P), fp.encode([1 << (P - 1)], P), 1, P)
+            assert fp.decode(y) == [fp.round_half_even(hv << (P - 1), P)]
+    n, P = 300, 2000
+    h = si.uniform(2 * n - 1, P, (62,))
+    H = fp.decode(h)
+    for k in (0, 77, n - 1):
+        y, rc, _, _ = _oneshot("hankel", h, si.unit(n, P, k), n, P)
+        assert fp.decode(y) == H[k:k + n]
+
+
+def test_planned_reuse_and_info():
+    """One plan, several vectors: each result equals the oracle."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    n, P = 200, 3322
+    h = si.uniform(2 * n - 1, P, (63,))
+    plan = hmv.Plan("hankel", hmv.to_device(h), n, P, algo="split_fft")
+    info = plan.info()
+    assert info["algo"] == 1 and info["bound"] < 0.5 and 8 <= info["w"] <= 20
+    H = fp.decode(h)
+    for k in range(3):
+        x = si.uniform(n, P, (64, k))
+        y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+        announce("fft planned", k)
+        plan.matvec(hmv.to_device(x), y)
+        rc, flags, err = hmv.read_status(plan.ws)
+        assert rc == 0 and err <= info["bound"]
+        assert np.array_equal(hmv.to_host(y), fp.encode(hankel.matvec_ints("hankel", H, fp.decode(x), P), P))
+    plan.close()
+
+
+def test_forced_width_bound_refusal():
+    """A limb width the proven bound rejects is refused (EBOUND)."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    n, P = 1024, 33220
+    h = si.uniform(2 * n - 1, P, (65,))
+    hmv.force_width(20)
+    try:
+        with pytest.raises(hmv.HmvError) as ei:
+            hmv.Plan("hankel", hmv.to_device(h), n, P, algo="split_fft")
+        assert ei.value.code == hmv.EBOUND
+    finally:
+        hmv.force_width(0)
+
+
+def test_cross_path_equals_schoolbook():
+    need_gpu()
+    n, P = 256, 4096
+    h = si.uniform(2 * n - 1, P, (66,))
+    x = si.uniform(n, P, (67,))
+    announce("fft vs school", n, P)
+    y1, *_ = _oneshot("hankel", h, x, n, P, "split_fft")
+    y2, *_ = _oneshot("hankel", h, x, n, P, "schoolbook")
+    assert np.array_equal(y1, y2)
+
+
+def _sampled_rows_check(h, x, y, P, rows):
+    H, X = fp.decode(h), fp.decode(x)
+    want = hankel.matvec_rows("hankel", H, X, P, rows, processes=8)
+    got = fp.decode(y[rows])
+    assert got == want
+
+
+def test_hilbert_n1024_p33220():
+    """Configuration of the paper's precision: n = 1024, P = 33220, Hilbert h."""
+    need_gpu()
+    n, P = 1024, 33220
+    h, x = si.hilbert_case(n, P, seed=0)
+    announce("fft hilbert", n, P)
+    y, rc, flags, err = _oneshot("hankel", h, x, n, P)
+    assert rc == 0 and flags == 0
+    print("max rounding distance", err, flush=True)
+    rows = [0, 1, 511, 1022, 1023]
+    _sampled_rows_check(h, x, y, P, rows)
+    if kronecker.available():
+        assert np.array_equal(y, kronecker.hankel_matvec_words(h, x, P))
