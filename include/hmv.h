@@ -119,6 +119,13 @@ int hmv_plan_h(hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P
                void* plan_mem, int64_t plan_bytes, void* ws, int64_t ws_bytes, void* stream);
 int hmv_plan_matvec(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* ws,
                     int64_t ws_bytes, void* stream);
+/* Same as hmv_plan_matvec, and records caller-created HIP events (hipEvent_t,
+ * NULL entries skipped) on `stream` around the path's kernels, for per-kernel
+ * timing: split-FFT: events[0] before the limb-axis forward pass, [1] before
+ * the index-axis pass, [2] before the limb-axis inverse / carry pass, [3]
+ * after it.  Other algorithms record [0] and [3] only.                       */
+int hmv_plan_matvec_events(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* ws,
+                           int64_t ws_bytes, void* stream, void* const* events);
 int64_t hmv_plan_workspace_bytes(const hmv_plan* plan);
 int hmv_plan_info(const hmv_plan* plan, hmv_plan_info_t* info);
 int hmv_plan_destroy(hmv_plan* plan);

@@ -260,9 +260,27 @@ int row_threads(int M, int P, int W, int L, int w) {
 }
 int col_threads(int Nt) { return Nt / 16 < 64 ? 64 : Nt / 16; }
 
+// Raise a kernel's dynamic-LDS limit once per (device, kernel, size) so that
+// later launches (possibly under stream capture) make no attribute calls.
+std::mutex g_lds_mu;
+std::vector<std::pair<std::pair<int, const void*>, size_t>> g_lds_set;
+
 hipError_t set_lds(const void* fn, size_t bytes) {
   if (bytes <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_lds_mu);
+  for (auto& kv : g_lds_set)
+    if (kv.first.first == dev && kv.first.second == fn) {
+      if (kv.second >= bytes) return hipSuccess;
+      e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e == hipSuccess) kv.second = bytes;
+      return e;
+    }
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) g_lds_set.push_back({{dev, fn}, bytes});
+  return e;
 }
 }  // namespace
 

@@ -156,19 +156,28 @@ int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
   return HMV_OK;
 }
 
+hipError_t mark(void* const* ev, int k, hipStream_t s) {
+  if (!ev || !ev[k]) return hipSuccess;
+  return hipEventRecord(static_cast<hipEvent_t>(ev[k]), s);
+}
+
 int fft_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
-                    char* scratch, int64_t scratch_bytes, hipStream_t s) {
+                    char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* ev) {
   if (scratch_bytes < p->mv_scratch) return HMV_ENOMEM;
   const int n = (int)p->n;
   const int W = (int)words_of(p->P);
   double2* X1 = reinterpret_cast<double2*>(scratch);
   double2* Y1 = reinterpret_cast<double2*>(scratch + p->mv_scratch / 2);
-  hipError_t e = launch_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, st, s);
+  hipError_t e = mark(ev, 0, s);
+  if (e == hipSuccess) e = launch_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, st, s);
   if (e != hipSuccess) return status_from_hip(e, "rows fwd (x)");
-  e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, Y1, s);
+  e = mark(ev, 1, s);
+  if (e == hipSuccess) e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, Y1, s);
   if (e != hipSuccess) return status_from_hip(e, "cols pass");
   const int rev = (p->kind == HMV_HANKEL) ? 0 : 1;
-  e = launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, rev, y, st, s);
+  e = mark(ev, 2, s);
+  if (e == hipSuccess) e = launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, rev, y, st, s);
+  if (e == hipSuccess) e = mark(ev, 3, s);
   return status_from_hip(e, "rows inv");
 }
 
@@ -280,6 +289,11 @@ int hmv_plan_h(hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P
 
 int hmv_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, void* ws, int64_t ws_bytes,
                     void* stream) {
+  return hmv_plan_matvec_events(p, x, y, ws, ws_bytes, stream, nullptr);
+}
+
+int hmv_plan_matvec_events(const hmv_plan* p, const uint64_t* x, uint64_t* y, void* ws,
+                           int64_t ws_bytes, void* stream, void* const* events) {
   if (!p || !x || !y || !ws) return HMV_EINVAL;
   if (ws_bytes < kStatusBytes) return HMV_ENOMEM;
   clear_stale_error();
@@ -289,7 +303,8 @@ int hmv_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, void* ws,
   if (e != hipSuccess) return status_from_hip(e, "clear status");
   char* scratch = static_cast<char*>(ws) + kStatusBytes;
   const int64_t scratch_bytes = ws_bytes - kStatusBytes;
-  if (p->algo == HMV_SPLIT_FFT) return fft_plan_matvec(p, x, y, st, scratch, scratch_bytes, s);
+  if (p->algo == HMV_SPLIT_FFT)
+    return fft_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);
   return HMV_EUNSUPPORTED;
 }
 

@@ -40,6 +40,7 @@ SIGNATURES = {
                             _vp, _c_i64, _vp]),
     "hmv_plan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp]),
     "hmv_plan_workspace_bytes": (_c_i64, [_vp]),
+    "hmv_plan_matvec_events": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp, ctypes.POINTER(_vp)]),
     "hmv_plan_info": (_c_int, [_vp, _vp]),
     "hmv_plan_destroy": (_c_int, [_vp]),
     "hmv_fft_error_bound": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, _c_i32, ctypes.c_double]),
@@ -198,6 +199,17 @@ class Plan:
                                    _stream(stream))
         if check:
             _check(rc, "plan_matvec")
+        return rc
+
+    def matvec_events(self, x, y, events, ws=None, stream=None) -> int:
+        """Planned matvec recording 4 torch.cuda.Event objects around its kernels."""
+        ws = self.ws if ws is None else ws
+        arr = (_vp * 4)()
+        for k, ev in enumerate(events):
+            arr[k] = ctypes.c_void_p(ev.cuda_event) if ev is not None else None
+        rc = lib().hmv_plan_matvec_events(self.handle, _ptr(x), _ptr(y), _ptr(ws), ws.numel(),
+                                          _stream(stream), arr)
+        _check(rc, "plan_matvec_events")
         return rc
 
     def close(self):
