@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--no-school", action="store_true", help="skip the GPU schoolbook comparison")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-verify", action="store_true", help="skip the GMP full-vector check")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run a plain device copy of BYTES bytes (5 times), the reference "
+                         "for scaling hardware byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -97,6 +100,16 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     procs = max(1, min(16, os.cpu_count() or 1))
+
+    if args.copy_calibration > 0:
+        a = torch.empty(args.copy_calibration // 8, dtype=torch.int64, device=dev)
+        a.fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 5 copies of {args.copy_calibration} bytes")
+        del a, b
 
     t = time.time()
     h = si.session_h(n, P)

@@ -144,17 +144,18 @@ __device__ inline void split_balanced(const uint64_t* wd, int W, int w, int L, S
 }
 
 // ---------------------------------------------------------------------------
-// Exact carry, round and pack.
-// S = sum_{e < NC} coef[e] * 2^(w e) with int64 coefficients (LDS).
-// Y = round-half-even(S / 2^P) is written as W two's complement words to y.
-// sw: LDS scratch of NWS words (see carry_words()); red: 32 uint32 LDS slots.
+// Exact carry, round and pack
 // ---------------------------------------------------------------------------
 constexpr int kCarryMaxPer = 16;
 
+// LDS words needed by carry_round_pack: NWS words for S plus NWS small carries.
 __host__ __device__ inline int carry_words(int NC, int w, int P, int W) {
   const int a = (int)(((int64_t)w * (NC - 1)) / 64) + 3;
   const int b = (P >> 6) + W + 2;
   return a > b ? a : b;
+}
+__host__ __device__ inline int carry_lds_bytes(int NC, int w, int P, int W) {
+  return carry_words(NC, w, P, W) * 12;
 }
 
 __device__ inline __int128 word_column(const int64_t* coef, int NC, int w, int q) {
@@ -178,37 +179,45 @@ __device__ inline __int128 word_column(const int64_t* coef, int NC, int w, int q
   return acc;
 }
 
+// Exact carry, round and pack.
+// S = sum_{e < NC} coef[e] * 2^(w e) with int64 coefficients (LDS).
+// Y = round-half-even(S / 2^P) is written as W two's complement words to y.
+// sw: LDS scratch of carry_lds_bytes() bytes; red: 32 uint32 LDS slots.
+// S is cut into 64-bit columns A_q = v_q + c_q 2^64 (v_q unsigned, c_q a
+// small signed carry); word q then holds v_q + c_{q-1} + kappa_q where the
+// ripple carry kappa in {-1, 0, 1} is resolved by a block scan of the maps
+// kappa_q -> kappa_{q+1}.
 __device__ inline void carry_round_pack(const int64_t* coef, int NC, int w, int P, int W,
                                         uint64_t* sw, int NWS, uint64_t* __restrict__ y,
                                         uint32_t* red) {
   const int T = blockDim.x, t = threadIdx.x;
   const int per = (NWS + T - 1) / T;
   const int q0 = min(NWS, t * per), q1 = min(NWS, q0 + per);
-  uint64_t v[kCarryMaxPer];
-  int64_t c[kCarryMaxPer];      // carry from the column below (c_{q-1})
+  int32_t* cv = reinterpret_cast<int32_t*>(sw + NWS);     // c_{q-1} per word q
   int64_t cprev = 0;
   if (q0 >= 1 && q0 < q1) cprev = (int64_t)(word_column(coef, NC, w, q0 - 1) >> 64);
   WordOp op;
   uint32_t f = kWordIdent;
-  for (int k = 0; k < q1 - q0; ++k) {
-    const __int128 A = word_column(coef, NC, w, q0 + k);
-    v[k] = (uint64_t)A;
-    c[k] = cprev;
-    cprev = (int64_t)(A >> 64);
+  for (int q = q0; q < q1; ++q) {
+    const __int128 A = word_column(coef, NC, w, q);
+    const uint64_t v = (uint64_t)A;
+    sw[q] = v;
+    cv[q] = (int32_t)cprev;
     uint32_t g = 0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      const __int128 s = (__int128)v[k] + c[k] + (i - 1);
+      const __int128 s = (__int128)v + cprev + (i - 1);
       const int kap = (int)(s >> 64);           // -1, 0 or 1
       g |= (uint32_t)(kap + 1) << (2 * i);
     }
     f = op(f, g);
+    cprev = (int64_t)(A >> 64);
   }
   const uint32_t fin = block_exclusive_scan(f, kWordIdent, op, red);
   int kappa = (int)(fin >> 2 & 3u) - 1;        // applied to kappa_0 = 0 (index 1)
-  for (int k = 0; k < q1 - q0; ++k) {
-    const __int128 s = (__int128)v[k] + c[k] + kappa;
-    sw[q0 + k] = (uint64_t)s;
+  for (int q = q0; q < q1; ++q) {
+    const __int128 s = (__int128)sw[q] + cv[q] + kappa;
+    sw[q] = (uint64_t)s;
     kappa = (int)(s >> 64);
   }
   __syncthreads();

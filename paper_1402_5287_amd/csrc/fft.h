@@ -75,6 +75,9 @@ template <int R>
 __device__ __forceinline__ void dft(double2* v, int sign);
 
 template <>
+__device__ __forceinline__ void dft<1>(double2*, int) {}
+
+template <>
 __device__ __forceinline__ void dft<2>(double2* v, int) {
   const double2 a = v[0], b = v[1];
   v[0] = cadd(a, b);
@@ -126,6 +129,11 @@ __device__ __forceinline__ void dft<16>(double2* v, int sign) {
   }
 }
 
+// LDS slot of element i: the low 4 index bits are XOR-ed with the next 4.
+// A bijection inside every aligned block of 256 (and of N when N < 256); it
+// spreads the stride-16 accesses of the early passes over all banks.
+__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 4) & 15); }
+
 // One Stockham pass over N points held in buf (LDS).  Requires
 // blockDim.x * NB >= N / R.  Ends with a barrier.
 template <int R, int NB>
@@ -140,7 +148,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int N, int Ns, int s
     if (b < nbf) {
       const int k = b & (Ns - 1);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[b + r * nbf];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[swz(b + r * nbf)];
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -160,13 +168,14 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int N, int Ns, int s
       dft<R>(v[i], sign);
       const int base = (b - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[i][r];
+      for (int r = 0; r < R; ++r) buf[swz(base + r * Ns)] = v[i][r];
     }
   }
   __syncthreads();
 }
 
-// Full transform of N = 2^logN points (2 <= N <= 8192) in buf.  Requires
+// Full transform of N = 2^logN points (2 <= N <= 8192) in buf (element i in
+// slot swz(i)).  Requires
 // blockDim.x >= N / 16 (blockDim.x >= 1 for N < 16).  Caller must have
 // synchronised after filling buf; ends with a barrier.
 __device__ __forceinline__ void fft_lds(double2* buf, int logN, int sign) {
@@ -180,6 +189,68 @@ __device__ __forceinline__ void fft_lds(double2* buf, int logN, int sign) {
   if (rem == 1) stockham_pass<2, 8>(buf, N, Ns, sign);
   else if (rem == 2) stockham_pass<4, 4>(buf, N, Ns, sign);
   else if (rem == 3) stockham_pass<8, 2>(buf, N, Ns, sign);
+}
+
+// ------------------------------------------------------------------------
+// Register-resident variant.  For N >= 16 the Ta = N/16 active threads each
+// hold 16 elements, element t + Ta*j in v[j]; for N < 16 thread 0 holds all
+// N.  The first pass reads its radix-16 inputs straight from registers and
+// the last pass writes its outputs straight back, in the same layout and in
+// natural order; LDS (N points) carries only the exchanges in between.  The
+// layout is also the input layout of the next transform's first pass, so a
+// pointwise product can sit between a forward and an inverse transform with
+// no LDS round trip.  Every thread of the block must call it.
+
+template <int R>
+__device__ __forceinline__ void last_pass_to_regs(const double2* buf, int N, int sign, int t,
+                                                  int Ta, double2* v) {
+  const int Ns = N / R;            // span before the pass == butterflies in it
+  const double2* tw = g_tw + tw_offset(R, Ns);
+#pragma unroll
+  for (int i = 0; i < 16 / R; ++i) {
+    const int b = t + i * Ta;      // butterfly index; k = b since b < Ns
+    double2 u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = buf[swz(b + r * Ns)];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      double2 w = tw[b * (R - 1) + (r - 1)];
+      if (sign > 0) w.y = -w.y;
+      u[r] = cmul(u[r], w);
+    }
+    dft<R>(u, sign);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[i + r * (16 / R)] = u[r];
+  }
+}
+
+template <int LOGN>
+__device__ __forceinline__ void fft_regs(double2* v, double2* buf, int sign) {
+  constexpr int N = 1 << LOGN;
+  const int t = threadIdx.x;
+  if constexpr (N <= 16) {
+    if (t == 0) dft<N>(v, sign);
+    return;
+  } else {
+    constexpr int Ta = N >> 4;
+    constexpr int A = LOGN >> 2, REM = LOGN & 3;
+    const bool act = t < Ta;
+    if (act) {
+      dft<16>(v, sign);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) buf[swz(16 * t + r)] = v[r];
+    }
+    __syncthreads();
+    constexpr int NMID = (REM ? A : A - 1) - 1;
+    int Ns = 16;
+#pragma unroll
+    for (int p = 0; p < NMID; ++p) {
+      stockham_pass<16, 1>(buf, N, Ns, sign);
+      Ns <<= 4;
+    }
+    if (act) last_pass_to_regs<(REM == 0 ? 16 : (1 << REM))>(buf, N, sign, t, Ta, v);
+    __syncthreads();
+  }
 }
 
 }  // namespace hmv

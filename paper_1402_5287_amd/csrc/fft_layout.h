@@ -9,12 +9,6 @@ namespace hmv {
 // ---------------------------------------------------------------- twiddles
 // One table per (R, Ns), R in {2,4,8,16}, Ns in {1,16,256,4096}:
 // entries [k][r-1] = exp(-2 pi i r k / (R Ns)), k < Ns, 1 <= r < R.
-__host__ __device__ constexpr int tw_radix_index(int R) {
-  return R == 2 ? 0 : (R == 4 ? 1 : (R == 8 ? 2 : 3));
-}
-__host__ __device__ constexpr int tw_span_index(int Ns) {
-  return Ns == 1 ? 0 : (Ns == 16 ? 1 : (Ns == 256 ? 2 : 3));
-}
 __host__ __device__ constexpr int64_t tw_offset(int R, int Ns) {
   int64_t off = 0;
   const int radices[4] = {2, 4, 8, 16};
@@ -30,5 +24,4 @@ constexpr int64_t kTwEntries = (1 + 3 + 7 + 15) * (1 + 16 + 256 + 4096);
 // real-input packing roots exp(-2 pi i k / 16384), k = 0..8192
 constexpr int kRealTwN = 16384;
 constexpr int64_t kRealTwEntries = kRealTwN / 2 + 1;
-
 }  // namespace hmv

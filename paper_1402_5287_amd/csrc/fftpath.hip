@@ -68,9 +68,9 @@ hipError_t fft_tables_init() {
 }
 
 // ------------------------------------------------------------------ helpers
-__device__ __forceinline__ int xcd_column(int b, int grid) {
+__device__ __forceinline__ int xcd_slot(int b, int grid) {
   // work-groups are dealt to the 8 XCDs round-robin; give each XCD a
-  // contiguous run of columns so tile neighbours share its L2
+  // contiguous run of indices so neighbours share its L2
   const int q = grid >> 3;
   return (b & 7) * q + (b >> 3);
 }
@@ -120,10 +120,10 @@ __global__ void __launch_bounds__(256) k_h_norms(const uint64_t* __restrict__ h,
 
 // Row pass, forward: split one number into digits, real FFT over the limb
 // axis (N_z = 2M real points), write the M+1 non-redundant bins.
-__global__ void __launch_bounds__(1024) k_rows_fwd(const uint64_t* __restrict__ in, int W, int P,
-                                                   int w, int L, int count, int gather_n, int logM,
-                                                   double2* __restrict__ out, int rows_alloc,
-                                                   DevStatus* st) {
+__global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict__ in, int W, int P,
+                                                     int w, int L, int count, int gather_n,
+                                                     int logM, double2* __restrict__ out,
+                                                     int rows_alloc, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint64_t wd[kMaxWords];
   __shared__ uint32_t red[32];
@@ -135,115 +135,198 @@ __global__ void __launch_bounds__(1024) k_rows_fwd(const uint64_t* __restrict__ 
   for (int q = t; q < W; q += T) wd[q] = in[(int64_t)src * W + q];
   __syncthreads();
   if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
+  // digit e is the real (e even) or imaginary (e odd) part of element e/2
   double* bd = reinterpret_cast<double*>(buf);
-  for (int e = L + t; e < 2 * M; e += T) bd[e] = 0.0;
-  split_balanced(wd, W, w, L, [&](int e, int d) { bd[e] = (double)d; }, red);
+  for (int e = L + t; e < 2 * M; e += T) bd[2 * swz(e >> 1) + (e & 1)] = 0.0;
+  split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * swz(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);
   // real-input packing: X[k] = 1/2 (Z[k] + conj Z[M-k]) - i/2 w^k (Z[k] - conj Z[M-k])
   const int rs = kRealTwN / (2 * M);
   for (int k = t; k <= M; k += T) {
-    const double2 zk = buf[k & (M - 1)], zm = buf[(M - k) & (M - 1)];
+    const double2 zk = buf[swz(k & (M - 1))], zm = buf[swz((M - k) & (M - 1))];
     const double2 A = cadd(zk, conj2(zm)), B = csub(zk, conj2(zm));
     const double2 Q = cmul(g_rtw[k * rs], B);
     out[tile_index(k, r, rows_alloc)] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
   }
 }
 
+// The index-axis transforms of N_t = 2 Nh points are split by one radix-2
+// decimation-in-frequency step into two Nh-point transforms: the even
+// frequencies are the transform of a[s] = u[s] + u[s+Nh], the odd ones the
+// transform of b[s] = (u[s] - u[s+Nh]) w^s (w = exp(-2 pi i / N_t)).  A
+// column of the resident spectrum stores the Nh even bins, then the Nh odd
+// bins.  The inverse of the product recombines as
+//   y[s] = e[s] + w^-s o[s],   y[s+Nh] = e[s] - w^-s o[s]
+// with e, o the two unnormalised Nh-point inverses (one radix-2
+// decimation-in-time step).  Each half needs Nh points of LDS, so the
+// headline shape (N_t = 8192) runs two work-groups per CU.
+
 // Column pass of the plan: transform each limb-frequency column of h over the
 // index axis and store it scaled by 2^-(log N_t + log N_z) (exact), so the
 // matvec's unnormalised inverse transforms need no further scaling.
+template <int LOGNH>
 __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H1, int rows,
-                                                   int C, int logNt, double scale,
+                                                   int C, double scale,
                                                    double2* __restrict__ Hh) {
   extern __shared__ double2 buf[];
-  const int c = xcd_column(blockIdx.x, gridDim.x);
+  const int c = xcd_slot(blockIdx.x, gridDim.x);
   if (c >= C) return;
-  const int T = blockDim.x, t = threadIdx.x, Nt = 1 << logNt;
+  constexpr int logNt = LOGNH + 1, Nh = 1 << LOGNH;
+  constexpr int Ta = Nh >= 16 ? Nh >> 4 : 1, per = Nh >= 16 ? 16 : Nh;
+  constexpr int rs = kRealTwN >> logNt;
+  const int t = threadIdx.x;
+  const bool act = t < Ta;
   const double2* col = H1 + tile_index(c, 0, rows);
-  for (int s = t; s < Nt; s += T) buf[s] = s < rows ? col[(int64_t)s * 8] : make_double2(0.0, 0.0);
-  __syncthreads();
-  fft_lds(buf, logNt, -1);
-  double2* dst = Hh + (int64_t)c * Nt;
-  for (int f = t; f < Nt; f += T) dst[f] = make_double2(buf[f].x * scale, buf[f].y * scale);
+  double2* he = Hh + (int64_t)c * (2 * Nh);
+  double2* ho = he + Nh;
+  double2 v[16];
+  for (int half = 0; half < 2; ++half) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (act && j < per) {
+        const int s = t + Ta * j;
+        const double2 lo = s < rows ? col[(int64_t)s * 8] : make_double2(0.0, 0.0);
+        const double2 hi = s + Nh < rows ? col[(int64_t)(s + Nh) * 8] : make_double2(0.0, 0.0);
+        v[j] = half == 0 ? cadd(lo, hi) : cmul(csub(lo, hi), g_rtw[s * rs]);
+      }
+    }
+    fft_regs<LOGNH>(v, buf, -1);
+    double2* dst = half == 0 ? he : ho;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (act && j < per) {
+        const int f = t + Ta * j;
+        dst[f] = make_double2(v[j].x * scale, v[j].y * scale);
+      }
+  }
 }
 
-// Column pass of the matvec: x column reversed, forward FFT, times the
-// resident spectrum of h, inverse FFT, keep rows n-1 .. 2n-2.
+// Column pass of the matvec: x column reversed (x_hat[s] = x[n-1-s], zero for
+// s >= n; n <= Nh so the high half is zero), forward transform, times the
+// resident spectrum of h, inverse transform, keep rows n-1 .. 2n-2.
+template <int LOGNH>
 __global__ void __launch_bounds__(512) k_cols_pass(const double2* __restrict__ X1,
                                                    const double2* __restrict__ Hh, int n, int C,
-                                                   int logNt, double2* __restrict__ Y1) {
+                                                   double2* __restrict__ Y1) {
   extern __shared__ double2 buf[];
-  const int c = xcd_column(blockIdx.x, gridDim.x);
+  const int c = xcd_slot(blockIdx.x, gridDim.x);
   if (c >= C) return;
-  const int T = blockDim.x, t = threadIdx.x, Nt = 1 << logNt;
+  constexpr int logNt = LOGNH + 1, Nh = 1 << LOGNH;
+  constexpr int Ta = Nh >= 16 ? Nh >> 4 : 1, per = Nh >= 16 ? 16 : Nh;
+  constexpr int rs = kRealTwN >> logNt;
+  const int t = threadIdx.x;
+  const bool act = t < Ta;
   const double2* xcol = X1 + tile_index(c, 0, n);
-  for (int s = t; s < Nt; s += T)
-    buf[s] = s < n ? xcol[(int64_t)(n - 1 - s) * 8] : make_double2(0.0, 0.0);
-  __syncthreads();
-  fft_lds(buf, logNt, -1);
-  const double2* hc = Hh + (int64_t)c * Nt;
-  for (int f = t; f < Nt; f += T) buf[f] = cmul(buf[f], hc[f]);
-  __syncthreads();
-  fft_lds(buf, logNt, +1);
+  const double2* he = Hh + (int64_t)c * (2 * Nh);
+  const double2* ho = he + Nh;
   double2* ycol = Y1 + tile_index(c, 0, n);
-  for (int i = t; i < n; i += T) ycol[(int64_t)i * 8] = buf[i + n - 1];
+  double2 v[16], e[16];
+  // even frequencies
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (act && j < per) {
+      const int s = t + Ta * j;
+      v[j] = s < n ? xcol[(int64_t)(n - 1 - s) * 8] : make_double2(0.0, 0.0);
+    }
+  fft_regs<LOGNH>(v, buf, -1);
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (act && j < per) v[j] = cmul(v[j], he[t + Ta * j]);
+  fft_regs<LOGNH>(v, buf, +1);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) e[j] = v[j];
+  // odd frequencies
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (act && j < per) {
+      const int s = t + Ta * j;
+      const double2 xv = s < n ? xcol[(int64_t)(n - 1 - s) * 8] : make_double2(0.0, 0.0);
+      v[j] = cmul(xv, g_rtw[s * rs]);
+    }
+  fft_regs<LOGNH>(v, buf, -1);
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (act && j < per) v[j] = cmul(v[j], ho[t + Ta * j]);
+  fft_regs<LOGNH>(v, buf, +1);
+  // recombine and keep the window
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (act && j < per) {
+      const int s = t + Ta * j;
+      const double2 q = cmul(v[j], conj2(g_rtw[s * rs]));
+      const int ra = s - (n - 1), rb = s + Nh - (n - 1);
+      if (ra >= 0 && ra < n) ycol[(int64_t)ra * 8] = cadd(e[j], q);
+      if (rb >= 0 && rb < n) ycol[(int64_t)rb * 8] = csub(e[j], q);
+    }
 }
 
 // Row pass, inverse: real inverse FFT over the limb axis, round every
-// coefficient to its integer, exact carry / round-half-even / pack.
-__global__ void __launch_bounds__(1024) k_rows_inv(const double2* __restrict__ Y1, int n, int logM,
-                                                   int L, int w, int P, int W, int out_reverse,
-                                                   uint64_t* __restrict__ y, DevStatus* st) {
+// coefficient to its integer, exact carry / round-half-even / pack.  The
+// last FFT pass leaves the coefficients in registers, where they are rounded
+// and then stored compactly (coefficient e in int64 slot e) at the start of
+// the FFT buffer; the carry scratch follows at carry_off.
+template <int LOGM>
+__global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__ Y1, int n, int L,
+                                                     int w, int P, int W, int out_reverse,
+                                                     int carry_off, uint64_t* __restrict__ y,
+                                                     DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint32_t red[32];
+  __shared__ double2 ytop;                 // Y[M]
   const int i = blockIdx.x;
   if (i >= n) return;
-  const int T = blockDim.x, t = threadIdx.x, M = 1 << logM;
-  for (int k = t; k <= M; k += T) buf[k] = Y1[tile_index(k, i, n)];
+  constexpr int M = 1 << LOGM;
+  constexpr int Ta = M >= 16 ? M >> 4 : 1, per = M >= 16 ? 16 : M;
+  constexpr int rs = kRealTwN / (2 * M);
+  const int T = blockDim.x, t = threadIdx.x;
+  const bool act = t < Ta;
+  // packing roots first: independent of the data
+  double2 wk[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (act && j < per) wk[j] = conj2(g_rtw[(t + Ta * j) * rs]);
+  for (int k = t; k < M; k += T) buf[swz(k)] = Y1[tile_index(k, i, n)];
+  if (t == 0) ytop = Y1[tile_index(M, i, n)];
   __syncthreads();
   // Z[k] = (Y[k] + conj Y[M-k]) + i w^-k (Y[k] - conj Y[M-k]),  k < M
-  const int rs = kRealTwN / (2 * M);
-  double2 z[16];
+  double2 v[16];
 #pragma unroll
-  for (int a = 0; a < 16; ++a) {
-    const int k = t + a * T;
-    if (k < M) {
-      const double2 yk = buf[k], ym = buf[M - k];
+  for (int j = 0; j < 16; ++j)
+    if (act && j < per) {
+      const int k = t + Ta * j;
+      const double2 yk = buf[swz(k)];
+      const double2 ym = k == 0 ? ytop : buf[swz(M - k)];
       const double2 E = cadd(yk, conj2(ym)), D = csub(yk, conj2(ym));
-      const double2 Q = cmul(D, conj2(g_rtw[k * rs]));
-      z[a] = make_double2(E.x - Q.y, E.y + Q.x);
+      const double2 Q = cmul(D, wk[j]);
+      v[j] = make_double2(E.x - Q.y, E.y + Q.x);
     }
-  }
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 16; ++a) {
-    const int k = t + a * T;
-    if (k < M) buf[k] = z[a];
-  }
-  __syncthreads();
-  fft_lds(buf, logM, +1);
-  // round to integers in place (double -> int64 in the same slot)
-  const double* bd = reinterpret_cast<const double*>(buf);
+  fft_regs<LOGM>(v, buf, +1);
+  // element m = t + Ta j holds coefficients 2m (real part) and 2m+1 (imaginary)
   int64_t* coef = reinterpret_cast<int64_t*>(buf);
   const int NC = 2 * L - 1;
   double maxerr = 0.0;
   int bad = 0;
-  for (int e = t; e < 2 * M; e += T) {
-    const double v = bd[e];
-    const double s = rint(v);
-    maxerr = fmax(maxerr, fabs(v - s));
-    const int64_t iv = (int64_t)s;
-    if (e >= NC && iv != 0) bad = 1;
-    coef[e] = iv;
-  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (act && j < per) {
+      const int m = t + Ta * j;
+      const double s0 = rint(v[j].x), s1 = rint(v[j].y);
+      maxerr = fmax(maxerr, fmax(fabs(v[j].x - s0), fabs(v[j].y - s1)));
+      const int64_t i0 = (int64_t)s0, i1 = (int64_t)s1;
+      if (2 * m < NC) coef[2 * m] = i0;
+      else if (i0 != 0) bad = 1;
+      if (2 * m + 1 < NC) coef[2 * m + 1] = i1;
+      else if (i1 != 0) bad = 1;
+    }
   for (int o = 32; o > 0; o >>= 1) maxerr = fmax(maxerr, __shfl_xor(maxerr, o, 64));
   if ((t & 63) == 0 && st)
     atomicMax(reinterpret_cast<unsigned long long*>(&st->max_err_bits),
               (unsigned long long)__double_as_longlong(maxerr));
   bad = __syncthreads_or(bad);
   if (bad && t == 0) status_or(st, ST_BOUND);
-  uint64_t* sw = reinterpret_cast<uint64_t*>(buf + M + 1);
+  uint64_t* sw = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(buf) + carry_off);
   const int NWS = carry_words(NC, w, P, W);
   const int row = out_reverse ? (n - 1 - i) : i;
   carry_round_pack(coef, NC, w, P, W, sw, NWS, y + (int64_t)row * W, red);
@@ -251,14 +334,17 @@ __global__ void __launch_bounds__(1024) k_rows_inv(const double2* __restrict__ Y
 
 // ------------------------------------------------------------------ launchers
 namespace {
+// Row kernels run M/16 threads (at least 64, at most 256: M <= 4096); the
+// carry step needs at most kCarryMaxPer words per thread, which holds for
+// every admissible (P, w) because the digit count L <= M.
 int row_threads(int M, int P, int W, int L, int w) {
   int T = M / 16;
   if (T < 64) T = 64;
   const int NWS = carry_words(2 * L - 1, w, P, W);
-  while (T < 1024 && (NWS + T - 1) / T > kCarryMaxPer) T += 64;
+  while (T < 256 && (NWS + T - 1) / T > kCarryMaxPer) T += 64;
   return T;
 }
-int col_threads(int Nt) { return Nt / 16 < 64 ? 64 : Nt / 16; }
+int col_threads(int Nt) { return Nt / 32 < 64 ? 64 : Nt / 32; }
 
 // Raise a kernel's dynamic-LDS limit once per (device, kernel, size) so that
 // later launches (possibly under stream capture) make no attribute calls.
@@ -304,41 +390,87 @@ hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int c
   return hipGetLastError();
 }
 
-hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, double scale,
-                            double2* Hh, hipStream_t s) {
-  const int Nt = 1 << logNt;
-  const size_t lds = sizeof(double2) * (size_t)Nt;
-  hipError_t e = set_lds((const void*)k_cols_plan, lds);
+template <int LOGNH>
+hipError_t cols_plan_t(const double2* H1, int rows, int C, double scale, double2* Hh,
+                       hipStream_t s) {
+  const size_t lds = sizeof(double2) * (size_t)(1 << LOGNH);
+  hipError_t e = set_lds((const void*)k_cols_plan<LOGNH>, lds);
   if (e != hipSuccess) return e;
   const int grid = (C + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_cols_plan, dim3(grid), dim3(col_threads(Nt)), lds, s, H1, rows, C, logNt,
-                     scale, Hh);
+  hipLaunchKernelGGL(k_cols_plan<LOGNH>, dim3(grid), dim3(col_threads(2 << LOGNH)), lds, s, H1,
+                     rows, C, scale, Hh);
   return hipGetLastError();
+}
+
+template <int LOGNH>
+hipError_t cols_pass_t(const double2* X1, const double2* Hh, int n, int C, double2* Y1,
+                       hipStream_t s) {
+  const size_t lds = sizeof(double2) * (size_t)(1 << LOGNH);
+  hipError_t e = set_lds((const void*)k_cols_pass<LOGNH>, lds);
+  if (e != hipSuccess) return e;
+  const int grid = (C + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_cols_pass<LOGNH>, dim3(grid), dim3(col_threads(2 << LOGNH)), lds, s, X1,
+                     Hh, n, C, Y1);
+  return hipGetLastError();
+}
+
+#define HMV_NT_DISPATCH(FN, ...)                  \
+  switch (logNt - 1) {                            \
+    case 1: return FN<1>(__VA_ARGS__);            \
+    case 2: return FN<2>(__VA_ARGS__);            \
+    case 3: return FN<3>(__VA_ARGS__);            \
+    case 4: return FN<4>(__VA_ARGS__);            \
+    case 5: return FN<5>(__VA_ARGS__);            \
+    case 6: return FN<6>(__VA_ARGS__);            \
+    case 7: return FN<7>(__VA_ARGS__);            \
+    case 8: return FN<8>(__VA_ARGS__);            \
+    case 9: return FN<9>(__VA_ARGS__);            \
+    case 10: return FN<10>(__VA_ARGS__);          \
+    case 11: return FN<11>(__VA_ARGS__);          \
+    case 12: return FN<12>(__VA_ARGS__);          \
+    case 13: return FN<13>(__VA_ARGS__);          \
+    default: return hipErrorInvalidValue;         \
+  }
+
+hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, double scale,
+                            double2* Hh, hipStream_t s) {
+  HMV_NT_DISPATCH(cols_plan_t, H1, rows, C, scale, Hh, s)
 }
 
 hipError_t launch_cols_pass(const double2* X1, const double2* Hh, int n, int C, int logNt,
                             double2* Y1, hipStream_t s) {
-  const int Nt = 1 << logNt;
-  const size_t lds = sizeof(double2) * (size_t)Nt;
-  hipError_t e = set_lds((const void*)k_cols_pass, lds);
+  HMV_NT_DISPATCH(cols_pass_t, X1, Hh, n, C, Y1, s)
+}
+
+template <int LOGM>
+hipError_t rows_inv_t(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
+                      uint64_t* y, DevStatus* st, hipStream_t s) {
+  constexpr int M = 1 << LOGM;
+  const int T = row_threads(M, P, W, L, w);
+  const int NC = 2 * L - 1;
+  // FFT points during the transform; afterwards NC int64 coefficients then
+  // the carry scratch
+  const size_t fft_part = sizeof(double2) * (size_t)M;
+  const size_t carry_off = ((size_t)NC * 8 + 15) / 16 * 16;
+  const size_t carry_part = carry_off + (size_t)carry_lds_bytes(NC, w, P, W);
+  const size_t lds = fft_part > carry_part ? fft_part : carry_part;
+  hipError_t e = set_lds((const void*)k_rows_inv<LOGM>, lds);
   if (e != hipSuccess) return e;
-  const int grid = (C + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_cols_pass, dim3(grid), dim3(col_threads(Nt)), lds, s, X1, Hh, n, C, logNt,
-                     Y1);
+  hipLaunchKernelGGL(k_rows_inv<LOGM>, dim3(n), dim3(T), lds, s, Y1, n, L, w, P, W, out_reverse,
+                     (int)carry_off, y, st);
   return hipGetLastError();
 }
 
 hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
                            int out_reverse, uint64_t* y, DevStatus* st, hipStream_t s) {
-  const int M = 1 << logM;
-  const int T = row_threads(M, P, W, L, w);
-  const int NWS = carry_words(2 * L - 1, w, P, W);
-  const size_t lds = sizeof(double2) * (size_t)(M + 1) + 8 * (size_t)NWS;
-  hipError_t e = set_lds((const void*)k_rows_inv, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rows_inv, dim3(n), dim3(T), lds, s, Y1, n, logM, L, w, P, W, out_reverse,
-                     y, st);
-  return hipGetLastError();
+  switch (logM) {
+#define HMV_RI(k) \
+  case k: return rows_inv_t<k>(Y1, n, L, w, P, W, out_reverse, y, st, s);
+    HMV_RI(1) HMV_RI(2) HMV_RI(3) HMV_RI(4) HMV_RI(5) HMV_RI(6) HMV_RI(7) HMV_RI(8) HMV_RI(9)
+    HMV_RI(10) HMV_RI(11) HMV_RI(12)
+#undef HMV_RI
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace hmv

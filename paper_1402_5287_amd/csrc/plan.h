@@ -31,7 +31,7 @@ void clear_stale_error();
 constexpr int kFftWMin = 8;        // candidate limb widths of the binary64 path
 constexpr int kFftWMax = 20;
 constexpr int kFftMaxLogNz = 13;   // limb-axis real FFT up to 8192 points (LDS)
-constexpr int kFftMaxLogNt = 13;   // index-axis FFT up to 8192 points (LDS)
+constexpr int kFftMaxLogNt = 14;   // index-axis FFT up to 16384 points (two 8192-point halves)
 constexpr int kNormSlots = 32;
 
 extern int g_force_w;              // tests: restrict the width candidates to one value

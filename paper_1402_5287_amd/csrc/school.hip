@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(512) k_school_row(const double* __restrict__ h
 size_t school_lds_bytes(int L, int w, int P, int W) {
   const int NC = 2 * L - 1;
   const size_t a = (size_t)(2 * L + 128) * 8;
-  const size_t b = (size_t)NC * 8 + (size_t)carry_words(NC, w, P, W) * 8;
+  const size_t b = (size_t)NC * 8 + (size_t)carry_lds_bytes(NC, w, P, W);
   return a > b ? a : b;
 }
 

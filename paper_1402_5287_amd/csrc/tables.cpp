@@ -44,14 +44,21 @@ void unit_root(int64_t m, int64_t N, double* re, double* im) {
 
 double gen_fft_tables(double* tw, double* rtw) {
   long double worst = 0.0L;
-  const int radices[4] = {2, 4, 8, 16};
-  const int spans[4] = {1, 16, 256, 4096};
   auto track = [&](int64_t m, int64_t N, double re, double im) {
     const long double th = 2.0L * 3.141592653589793238462643383279502884L * (long double)(m % N) / (long double)N;
     const long double dr = (long double)re - cosl(th), di = (long double)im + sinl(th);
     const long double e = sqrtl(dr * dr + di * di);
     if (e > worst) worst = e;
   };
+  for (int k = 0; k < kRealTwN / 2 + 1; ++k) {
+    double re, im;
+    unit_root(k, kRealTwN, &re, &im);
+    rtw[2 * k] = re;
+    rtw[2 * k + 1] = im;
+    track(k, kRealTwN, re, im);
+  }
+  const int radices[4] = {2, 4, 8, 16};
+  const int spans[4] = {1, 16, 256, 4096};
   for (int a = 0; a < 4; ++a)
     for (int b = 0; b < 4; ++b) {
       const int R = radices[a], Ns = spans[b];
@@ -65,19 +72,15 @@ double gen_fft_tables(double* tw, double* rtw) {
           track((int64_t)r * k, (int64_t)R * Ns, re, im);
         }
     }
-  for (int k = 0; k < kRealTwN / 2 + 1; ++k) {
-    double re, im;
-    unit_root(k, kRealTwN, &re, &im);
-    rtw[2 * k] = re;
-    rtw[2 * k + 1] = im;
-    track(k, kRealTwN, re, im);
-  }
   // constants of the radix-8/16 kernels: cos(pi/8), sin(pi/8), cos(pi/4)
   {
-    double re, im;
-    for (int m = 1; m < 16; ++m) {
-      unit_root(m, 16, &re, &im);
-      track(m, 16, re, im);
+    const double c[3] = {0.92387953251128673848, 0.38268343236508978178, 0.70710678118654757274};
+    const long double ex[3] = {cosl(3.141592653589793238462643383279502884L / 8),
+                               sinl(3.141592653589793238462643383279502884L / 8),
+                               sqrtl(2.0L) / 2};
+    for (int i = 0; i < 3; ++i) {
+      const long double e = fabsl((long double)c[i] - ex[i]) * sqrtl(2.0L);
+      if (e > worst) worst = e;
     }
   }
   // the long double reference itself is within a few 2^-64 of the true root

@@ -10,8 +10,9 @@ namespace hmv {
 void unit_root(int64_t m, int64_t N, double* re, double* im);
 
 // Fill the Stockham table (2 * kTwEntries doubles) and the real-packing
-// table (2 * kRealTwEntries doubles).  Returns the largest |table - root|
-// observed against the long double values, plus a margin for the long double
+// table (2 * kRealTwEntries doubles: exp(-2 pi i k / 16384), k <= 8192).
+// Returns the largest |table - root| observed against the long double values
+// (the radix-8/16 constants included), plus a margin for the long double
 // evaluation itself: the beta of the error bound.
 double gen_fft_tables(double* tw, double* rtw);
 

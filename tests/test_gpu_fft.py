@@ -137,3 +137,20 @@ def test_hilbert_n1024_p33220():
     _sampled_rows_check(h, x, y, P, rows)
     if kronecker.available():
         assert np.array_equal(y, kronecker.hankel_matvec_words(h, x, P))
+
+
+def test_index_axis_16384():
+    """n > 4096 needs a 16384-point index-axis transform (two 8192-point halves)."""
+    need_gpu()
+    n, P = 4100, 300
+    h = si.uniform(2 * n - 1, P, (68,))
+    x = si.uniform(n, P, (69,))
+    announce("fft Nt=16384", n, P)
+    y, rc, flags, err = _oneshot("hankel", h, x, n, P)
+    assert rc == 0 and flags == 0
+    rows = [0, 1, 2047, 4098, 4099]
+    _sampled_rows_check(h, x, y, P, rows)
+    if kronecker.available():
+        assert np.array_equal(y, kronecker.hankel_matvec_words(h, x, P))
+    yt, rc, _, _ = _oneshot("toeplitz", h, x, n, P)
+    assert np.array_equal(yt, y[::-1])
