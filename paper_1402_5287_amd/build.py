@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhmv.so")
 
-SOURCES = ["api.cpp", "plan.cpp", "tables.cpp", "status.hip", "school.hip", "fftpath.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "tables.cpp", "status.hip", "school.hip", "fftpath.hip",
+           "nttpath.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -43,3 +43,25 @@ hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int
                            int out_reverse, uint64_t* y, DevStatus* st, hipStream_t s);
 
 }  // namespace hmv
+
+namespace hmv {
+
+// exact paths modulo 2^64 - 2^32 + 1 (NTT and Karatsuba)
+hipError_t ntt_tables_init();
+hipError_t launch_ntt_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int count,
+                               int gather_n, int logN, uint64_t* out, int rows_alloc, int logT,
+                               DevStatus* st, hipStream_t s);
+hipError_t launch_ntt_rows_inv(const uint64_t* Y, int n, int logN, int L, int w, int P, int W,
+                               int out_reverse, int logT, uint64_t* y, DevStatus* st,
+                               hipStream_t s);
+hipError_t launch_ntt_cols_plan(const uint64_t* H1, int rows, int C, int logNt, uint64_t scale,
+                                uint64_t* Hh, hipStream_t s);
+hipError_t launch_ntt_cols_pass(const uint64_t* X1, const uint64_t* Hh, int n, int C, int logNt,
+                                uint64_t* Y1, hipStream_t s);
+hipError_t launch_kara_rowops(const int4* ops, int nops, const uint64_t* src, uint64_t* dst,
+                              int Nz, hipStream_t s);
+hipError_t launch_kara_leaves(const int4* rows, int nrows, const uint64_t* A, const uint64_t* X,
+                              uint64_t* Y, int Nz, hipStream_t s);
+hipError_t launch_ntt_scale(uint64_t* a, int64_t count, uint64_t scale, hipStream_t s);
+
+}  // namespace hmv

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -181,22 +182,318 @@ int fft_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus
   return status_from_hip(e, "rows inv");
 }
 
-int resolve_algo(int algo) {
-  if (algo == HMV_AUTO) return HMV_SPLIT_FFT;
-  return algo;
+// ------------------------------------------------------------------ exact paths
+// Largest limb width whose worst-case coefficient n L 4^(w-1) stays below
+// 2^62 (so the centred residue mod p is the coefficient) and whose sizes fit.
+bool ntt_sizes_w(int64_t n, int32_t P, int w, NttSizes* z) {
+  const int L = limbs_of(P, w);
+  const long double cmax = (long double)n * L * std::ldexp(1.0L, 2 * (w - 1));
+  if (cmax >= std::ldexp(1.0L, 62)) return false;
+  int logNz = ilog2_ceil(2 * int64_t(L) - 1);
+  if (logNz < 2) logNz = 2;
+  int logNt = ilog2_ceil(2 * n - 1);
+  if (logNt < 2) logNt = 2;
+  if (logNz > kNttMaxLogNz || logNt > kNttMaxLogNt) return false;
+  z->w = w;
+  z->L = L;
+  z->logNz = logNz;
+  z->logNt = logNt;
+  z->Nz = int64_t(1) << logNz;
+  z->Nt = int64_t(1) << logNt;
+  z->cols_padded = (z->Nz + 15) / 16 * 16;
+  z->plan_bytes = align_up(8 * z->Nz * z->Nt);
+  z->plan_scratch = align_up(8 * z->cols_padded * (2 * n - 1));
+  z->mv_scratch = 2 * align_up(8 * z->cols_padded * n);
+  return true;
+}
+
+bool ntt_sizes(int64_t n, int32_t P, NttSizes* z) {
+  for (int w = 30; w >= 2; --w)
+    if (ntt_sizes_w(n, P, w, z)) return true;
+  return false;
+}
+
+int ntt_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
+                   int64_t scratch_bytes, char* plan_mem, int64_t plan_bytes, hipStream_t s) {
+  NttSizes z;
+  if (!ntt_sizes(p->n, p->P, &z)) return HMV_EUNSUPPORTED;
+  if (scratch_bytes < z.plan_scratch) return HMV_ENOMEM;
+  if (plan_bytes < z.plan_bytes) return HMV_ENOMEM;
+  hipError_t e = ntt_tables_init();
+  if (e != hipSuccess) return status_from_hip(e, "ntt tables");
+  const int n = (int)p->n, W = (int)words_of(p->P), rows = 2 * n - 1;
+  const int gather = (p->kind == HMV_CIRCULANT) ? n : 0;
+  p->w = z.w;
+  p->L = z.L;
+  p->logNz = z.logNz;
+  p->logNt = z.logNt;
+  p->Nt = z.Nt;
+  p->Nz = z.Nz;
+  p->cols_padded = z.cols_padded;
+  p->plan_bytes_used = z.plan_bytes;
+  p->mv_scratch = z.mv_scratch;
+  p->Hn = reinterpret_cast<uint64_t*>(plan_mem);
+  uint64_t* H1 = reinterpret_cast<uint64_t*>(scratch);
+  e = launch_ntt_rows_fwd(h, W, p->P, z.w, z.L, rows, gather, z.logNz, H1, rows, 4, st, s);
+  if (e != hipSuccess) return status_from_hip(e, "ntt rows fwd (h)");
+  const uint64_t scale = gold_inv(gold_mul((uint64_t)z.Nt, (uint64_t)z.Nz));
+  e = launch_ntt_cols_plan(H1, rows, (int)z.Nz, z.logNt, scale, p->Hn, s);
+  return status_from_hip(e, "ntt cols plan");
+}
+
+int ntt_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
+                    char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* ev) {
+  if (scratch_bytes < p->mv_scratch) return HMV_ENOMEM;
+  const int n = (int)p->n, W = (int)words_of(p->P);
+  uint64_t* X1 = reinterpret_cast<uint64_t*>(scratch);
+  uint64_t* Y1 = reinterpret_cast<uint64_t*>(scratch + p->mv_scratch / 2);
+  hipError_t e = mark(ev, 0, s);
+  if (e == hipSuccess)
+    e = launch_ntt_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logNz, X1, n, 4, st, s);
+  if (e != hipSuccess) return status_from_hip(e, "ntt rows fwd (x)");
+  e = mark(ev, 1, s);
+  if (e == hipSuccess) e = launch_ntt_cols_pass(X1, p->Hn, n, (int)p->Nz, p->logNt, Y1, s);
+  if (e != hipSuccess) return status_from_hip(e, "ntt cols pass");
+  const int rev = (p->kind == HMV_HANKEL) ? 0 : 1;
+  e = mark(ev, 2, s);
+  if (e == hipSuccess)
+    e = launch_ntt_rows_inv(Y1, n, p->logNz, p->L, p->w, p->P, W, rev, 4, y, st, s);
+  if (e == hipSuccess) e = mark(ev, 3, s);
+  return status_from_hip(e, "ntt rows inv");
+}
+
+// ---- Karatsuba (Section 4, Algorithm 1) over the index axis
+struct KaraTree {
+  int depth = 0;
+  int64_t rowsA = 0, rowsX = 0, rowsY = 0;
+  std::vector<std::vector<int4>> aops, xops, cops;   // per level (split l -> l+1, combine l+1 -> l)
+  std::vector<int4> leaf;
+  int64_t mults = 0;
+};
+
+// Breadth-first layout of the recursion of Algorithm 1 (0-based form):
+//   h_i = x_{2i}, f_i = x_{2i} - x_{2i+1}           (i < m,  x_n = 0)
+//   c_i = a_{2i} + a_{2i+1}, d_i = a_{2i+1}          (i < 2m-1, a_{2n-1} = 0)
+//   g_i = x_{2i-1} - x_{2i}                         (i < m1, x_{-1} = x_n = 0)
+//   e_i = a_{2i}                                    (i < 2m1-1, a_{2n-1} = a_{2n} = 0)
+//   p = C h, q = D f, r = E g;  y_{2i} = p_i - q_i, y_{2i+1} = p_i + r_i
+// with m = floor((n+1)/2), m1 = ceil((n+1)/2); sizes <= leaf use the plain
+// sum.  Rows of A (matrix vectors), X (vectors), Y (products) are numbered
+// globally; every op is (out row, in row a or -1, in row b or -1, sign).
+KaraTree kara_build(int64_t n, int leaf_max) {
+  struct Node { int64_t m, a, x, y; };
+  KaraTree T;
+  std::vector<Node> level = {{n, 0, 0, 0}};
+  T.rowsA = 2 * n - 1;
+  T.rowsX = n;
+  T.rowsY = n;
+  while (!level.empty()) {
+    std::vector<Node> next;
+    std::vector<int4> aops, xops, cops;
+    for (const Node& nd : level) {
+      const int64_t m = nd.m;
+      if (m <= leaf_max) {
+        for (int64_t i = 0; i < m; ++i)
+          T.leaf.push_back(make_int4((int)(nd.a + i), (int)nd.x, (int)(nd.y + i), (int)m));
+        T.mults += m * m;
+        continue;
+      }
+      const int64_t mc = (m + 1) / 2, m1 = (m + 2) / 2;
+      auto arow = [&](int64_t r) { return (r >= 0 && r <= 2 * m - 2) ? (int)(nd.a + r) : -1; };
+      auto xrow = [&](int64_t r) { return (r >= 0 && r < m) ? (int)(nd.x + r) : -1; };
+      Node C{mc, T.rowsA, T.rowsX, T.rowsY};
+      T.rowsA += 2 * mc - 1; T.rowsX += mc; T.rowsY += mc;
+      Node D{mc, T.rowsA, T.rowsX, T.rowsY};
+      T.rowsA += 2 * mc - 1; T.rowsX += mc; T.rowsY += mc;
+      Node E{m1, T.rowsA, T.rowsX, T.rowsY};
+      T.rowsA += 2 * m1 - 1; T.rowsX += m1; T.rowsY += m1;
+      for (int64_t i = 0; i < 2 * mc - 1; ++i) {
+        aops.push_back(make_int4((int)(C.a + i), arow(2 * i), arow(2 * i + 1), 1));
+        aops.push_back(make_int4((int)(D.a + i), -1, arow(2 * i + 1), 1));
+      }
+      for (int64_t i = 0; i < 2 * m1 - 1; ++i)
+        aops.push_back(make_int4((int)(E.a + i), arow(2 * i), -1, 1));
+      for (int64_t i = 0; i < mc; ++i) {
+        xops.push_back(make_int4((int)(C.x + i), xrow(2 * i), -1, 1));
+        xops.push_back(make_int4((int)(D.x + i), xrow(2 * i), xrow(2 * i + 1), -1));
+      }
+      for (int64_t i = 0; i < m1; ++i)
+        xops.push_back(make_int4((int)(E.x + i), xrow(2 * i - 1), xrow(2 * i), -1));
+      for (int64_t i = 0; i < mc; ++i) {
+        cops.push_back(make_int4((int)(nd.y + 2 * i), (int)(C.y + i), (int)(D.y + i), -1));
+        if (2 * i + 1 < m)
+          cops.push_back(make_int4((int)(nd.y + 2 * i + 1), (int)(C.y + i), (int)(E.y + i), 1));
+      }
+      next.push_back(C);
+      next.push_back(D);
+      next.push_back(E);
+    }
+    if (!next.empty()) {
+      T.aops.push_back(std::move(aops));
+      T.xops.push_back(std::move(xops));
+      T.cops.push_back(std::move(cops));
+    }
+    level.swap(next);
+  }
+  T.depth = (int)T.xops.size();
+  return T;
+}
+
+struct KaraSizes {
+  NttSizes z;
+  int64_t rowsA, rowsX, rowsY, nx, nc, nl, na;
+  int64_t plan_bytes, plan_scratch, mv_scratch;
+};
+
+bool kara_sizes(int64_t n, int32_t P, KaraSizes* k, KaraTree* tree_out) {
+  if (!ntt_sizes(n, P, &k->z)) return false;
+  KaraTree T = kara_build(n, kKaraLeaf);
+  if (T.rowsA > INT32_MAX / 2) return false;
+  k->rowsA = T.rowsA;
+  k->rowsX = T.rowsX;
+  k->rowsY = T.rowsY;
+  k->nx = k->nc = k->na = 0;
+  for (auto& v : T.xops) k->nx += (int64_t)v.size();
+  for (auto& v : T.cops) k->nc += (int64_t)v.size();
+  for (auto& v : T.aops) k->na += (int64_t)v.size();
+  k->nl = (int64_t)T.leaf.size();
+  const int64_t Nz = k->z.Nz;
+  k->plan_bytes = align_up(8 * Nz * T.rowsA) + align_up(16 * k->nx) + align_up(16 * k->nc) +
+                  align_up(16 * k->nl);
+  k->plan_scratch = align_up(16 * (k->na > 0 ? k->na : 1));
+  k->mv_scratch = align_up(8 * Nz * T.rowsX) + align_up(8 * Nz * T.rowsY);
+  if (tree_out) *tree_out = std::move(T);
+  return true;
+}
+
+int kara_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
+                    int64_t scratch_bytes, char* plan_mem, int64_t plan_bytes, hipStream_t s) {
+  KaraSizes k;
+  KaraTree T;
+  if (!kara_sizes(p->n, p->P, &k, &T)) return HMV_EUNSUPPORTED;
+  if (scratch_bytes < k.plan_scratch || plan_bytes < k.plan_bytes) return HMV_ENOMEM;
+  hipError_t e = ntt_tables_init();
+  if (e != hipSuccess) return status_from_hip(e, "ntt tables");
+  const int n = (int)p->n, W = (int)words_of(p->P), rows = 2 * n - 1;
+  const NttSizes& z = k.z;
+  const int64_t Nz = z.Nz;
+  p->w = z.w;
+  p->L = z.L;
+  p->logNz = z.logNz;
+  p->Nz = Nz;
+  p->Nt = 0;
+  p->rowsA = k.rowsA;
+  p->rowsX = k.rowsX;
+  p->rowsY = k.rowsY;
+  p->depth = T.depth;
+  p->leaves_mults = T.mults;
+  p->plan_bytes_used = k.plan_bytes;
+  p->mv_scratch = k.mv_scratch;
+  char* q = plan_mem;
+  p->Hn = reinterpret_cast<uint64_t*>(q);
+  q += align_up(8 * Nz * k.rowsA);
+  int4* d_x = reinterpret_cast<int4*>(q);
+  q += align_up(16 * k.nx);
+  int4* d_c = reinterpret_cast<int4*>(q);
+  q += align_up(16 * k.nc);
+  int4* d_l = reinterpret_cast<int4*>(q);
+  p->d_xops = d_x;
+  p->d_cops = d_c;
+  p->d_leaf = d_l;
+  p->nleaf = (int)k.nl;
+  // flatten the per-level op lists
+  std::vector<int4> xs, cs, as;
+  std::vector<int> aoff, acnt;
+  p->xops_off.clear();
+  p->xops_cnt.clear();
+  p->cops_off.clear();
+  p->cops_cnt.clear();
+  for (int l = 0; l < T.depth; ++l) {
+    p->xops_off.push_back((int)xs.size());
+    p->xops_cnt.push_back((int)T.xops[l].size());
+    xs.insert(xs.end(), T.xops[l].begin(), T.xops[l].end());
+    p->cops_off.push_back((int)cs.size());
+    p->cops_cnt.push_back((int)T.cops[l].size());
+    cs.insert(cs.end(), T.cops[l].begin(), T.cops[l].end());
+    aoff.push_back((int)as.size());
+    acnt.push_back((int)T.aops[l].size());
+    as.insert(as.end(), T.aops[l].begin(), T.aops[l].end());
+  }
+  int4* d_a = reinterpret_cast<int4*>(scratch);
+  if (!xs.empty()) e = hipMemcpyAsync(d_x, xs.data(), 16 * xs.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !cs.empty())
+    e = hipMemcpyAsync(d_c, cs.data(), 16 * cs.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !T.leaf.empty())
+    e = hipMemcpyAsync(d_l, T.leaf.data(), 16 * T.leaf.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !as.empty())
+    e = hipMemcpyAsync(d_a, as.data(), 16 * as.size(), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return status_from_hip(e, "karatsuba op lists");
+  // limb spectra of h (row-major), scaled by 1/N_z for the inverse transform
+  const int gather = (p->kind == HMV_CIRCULANT) ? n : 0;
+  e = launch_ntt_rows_fwd(h, W, p->P, z.w, z.L, rows, gather, z.logNz, p->Hn, rows, z.logNz, st, s);
+  if (e == hipSuccess) e = launch_ntt_scale(p->Hn, (int64_t)rows * Nz, gold_inv((uint64_t)Nz), s);
+  for (int l = 0; l < T.depth && e == hipSuccess; ++l)
+    e = launch_kara_rowops(d_a + aoff[l], acnt[l], p->Hn, p->Hn, (int)Nz, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // host op lists must outlive the copies
+  return status_from_hip(e, "karatsuba plan");
+}
+
+int kara_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
+                     char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* ev) {
+  if (scratch_bytes < p->mv_scratch) return HMV_ENOMEM;
+  const int n = (int)p->n, W = (int)words_of(p->P);
+  const int Nz = (int)p->Nz;
+  uint64_t* X = reinterpret_cast<uint64_t*>(scratch);
+  uint64_t* Y = reinterpret_cast<uint64_t*>(scratch + align_up(8 * p->Nz * p->rowsX));
+  hipError_t e = mark(ev, 0, s);
+  if (e == hipSuccess)
+    e = launch_ntt_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logNz, X, n, p->logNz, st, s);
+  for (int l = 0; l < p->depth && e == hipSuccess; ++l)
+    e = launch_kara_rowops(p->d_xops + p->xops_off[l], p->xops_cnt[l], X, X, Nz, s);
+  if (e == hipSuccess) e = mark(ev, 1, s);
+  if (e == hipSuccess) e = launch_kara_leaves(p->d_leaf, p->nleaf, p->Hn, X, Y, Nz, s);
+  for (int l = p->depth - 1; l >= 0 && e == hipSuccess; --l)
+    e = launch_kara_rowops(p->d_cops + p->cops_off[l], p->cops_cnt[l], Y, Y, Nz, s);
+  if (e == hipSuccess) e = mark(ev, 2, s);
+  const int rev = (p->kind == HMV_HANKEL) ? 0 : 1;
+  if (e == hipSuccess)
+    e = launch_ntt_rows_inv(Y, n, p->logNz, p->L, p->w, p->P, W, rev, p->logNz, y, st, s);
+  if (e == hipSuccess) e = mark(ev, 3, s);
+  return status_from_hip(e, "karatsuba matvec");
 }
 
 bool planned_sizes(int kind, int64_t n, int32_t P, int algo, int64_t* plan_b, int64_t* ws_b) {
   (void)kind;
-  algo = resolve_algo(algo);
-  if (algo == HMV_SPLIT_FFT) {
+  int64_t pb = 0, sb = 0;
+  bool ok = false;
+  if (algo == HMV_SPLIT_FFT || algo == HMV_AUTO) {
     FftSizes z;
-    if (!fft_worst_sizes(n, P, &z)) return false;
-    *plan_b = z.plan_bytes;
-    *ws_b = kStatusBytes + (z.plan_scratch > z.mv_scratch ? z.plan_scratch : z.mv_scratch);
-    return true;
+    if (fft_worst_sizes(n, P, &z)) {
+      pb = std::max(pb, z.plan_bytes);
+      sb = std::max(sb, std::max(z.plan_scratch, z.mv_scratch));
+      ok = true;
+    }
   }
-  return false;
+  if (algo == HMV_NTT || algo == HMV_AUTO) {
+    NttSizes z;
+    if (ntt_sizes(n, P, &z)) {
+      pb = std::max(pb, z.plan_bytes);
+      sb = std::max(sb, std::max(z.plan_scratch, z.mv_scratch));
+      ok = true;
+    }
+  }
+  if (algo == HMV_KARATSUBA) {
+    KaraSizes k;
+    if (kara_sizes(n, P, &k, nullptr)) {
+      pb = k.plan_bytes;
+      sb = std::max(k.plan_scratch, k.mv_scratch);
+      ok = true;
+    }
+  }
+  if (!ok) return false;
+  *plan_b = pb;
+  *ws_b = kStatusBytes + sb;
+  return true;
 }
 
 bool args_ok(int kind, int64_t n, int32_t P) {
@@ -252,8 +549,9 @@ int hmv_plan_h(hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P
   *out = nullptr;
   clear_stale_error();
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int a = resolve_algo(algo);
+  if (algo < HMV_AUTO || algo > HMV_KARATSUBA) return HMV_EINVAL;
   if (ws_bytes < kStatusBytes) return HMV_ENOMEM;
+  const int a = algo;
   hmv_plan* p = new (std::nothrow) hmv_plan();
   if (!p) return HMV_ENOMEM;
   p->kind = kind;
@@ -272,12 +570,22 @@ int hmv_plan_h(hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P
   }
   char* scratch = static_cast<char*>(ws) + kStatusBytes;
   const int64_t scratch_bytes = ws_bytes - kStatusBytes;
-  int rc;
-  if (a == HMV_SPLIT_FFT) {
-    rc = fft_plan_build(p, h, st, scratch, scratch_bytes, static_cast<char*>(plan_mem),
-                        plan_bytes, g_force_w, s);
-  } else {
-    rc = HMV_EUNSUPPORTED;
+  int rc = HMV_EUNSUPPORTED;
+  char* pm = static_cast<char*>(plan_mem);
+  if (a == HMV_SPLIT_FFT || a == HMV_AUTO) {
+    p->algo = HMV_SPLIT_FFT;
+    rc = fft_plan_build(p, h, st, scratch, scratch_bytes, pm, plan_bytes, g_force_w, s);
+    if (a == HMV_AUTO && (rc == HMV_EBOUND || rc == HMV_EUNSUPPORTED)) {
+      // no binary64 width passes the bound: fall back to the exact NTT path
+      p->algo = HMV_NTT;
+      e = launch_clear_status(st, s);
+      if (e != hipSuccess) rc = status_from_hip(e, "clear status");
+      else rc = ntt_plan_build(p, h, st, scratch, scratch_bytes, pm, plan_bytes, s);
+    }
+  } else if (a == HMV_NTT) {
+    rc = ntt_plan_build(p, h, st, scratch, scratch_bytes, pm, plan_bytes, s);
+  } else if (a == HMV_KARATSUBA) {
+    rc = kara_plan_build(p, h, st, scratch, scratch_bytes, pm, plan_bytes, s);
   }
   if (rc != HMV_OK) {
     delete p;
@@ -305,6 +613,9 @@ int hmv_plan_matvec_events(const hmv_plan* p, const uint64_t* x, uint64_t* y, vo
   const int64_t scratch_bytes = ws_bytes - kStatusBytes;
   if (p->algo == HMV_SPLIT_FFT)
     return fft_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);
+  if (p->algo == HMV_NTT) return ntt_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);
+  if (p->algo == HMV_KARATSUBA)
+    return kara_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);
   return HMV_EUNSUPPORTED;
 }
 

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace hmv {
 
 constexpr int64_t kAlign = 256;
@@ -42,6 +44,17 @@ struct FftSizes {
   int64_t plan_bytes, plan_scratch, mv_scratch;
 };
 
+// exact paths modulo 2^64 - 2^32 + 1
+constexpr int kNttMaxLogNz = 13;   // limb-axis transform up to 8192 residues (LDS)
+constexpr int kNttMaxLogNt = 14;
+constexpr int kKaraLeaf = 32;      // Algorithm 1 leaves: sizes <= 32 use the plain sum
+
+struct NttSizes {
+  int w, L, logNz, logNt;
+  int64_t Nt, Nz, cols_padded;
+  int64_t plan_bytes, plan_scratch, mv_scratch;
+};
+
 int ilog2_ceil(int64_t v);
 bool fft_sizes(int64_t n, int32_t P, int w, FftSizes* z);
 bool fft_worst_sizes(int64_t n, int32_t P, FftSizes* z);
@@ -64,4 +77,17 @@ struct hmv_plan {
   double bound = 0.0, beta = 0.0, norm_h = 0.0;
   int64_t plan_bytes_used = 0, mv_scratch = 0;
   double2* Hh = nullptr;           // resident spectrum of h (in caller plan memory)
+  // exact paths
+  int logNz = 0;
+  int64_t cols_padded = 0;
+  uint64_t* Hn = nullptr;          // NTT: resident spectrum; Karatsuba: limb spectra of the tree
+  // Karatsuba: breadth-first recursion tree as row-operation lists
+  int depth = 0;
+  int64_t rowsA = 0, rowsX = 0, rowsY = 0;
+  const int4* d_xops = nullptr;     // x-side splits, all levels
+  const int4* d_cops = nullptr;     // combines, all levels
+  const int4* d_leaf = nullptr;     // leaf rows
+  std::vector<int> xops_off, xops_cnt, cops_off, cops_cnt;
+  int nleaf = 0;
+  int64_t leaves_mults = 0;         // scalar products per limb column (Algorithm 1 count)
 };

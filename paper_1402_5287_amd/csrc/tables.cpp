@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "fft_layout.h"
+#include "ntt_layout.h"
 
 namespace hmv {
 
@@ -94,6 +95,58 @@ double fft_conv_bound(double norm_a, double norm_b, int k, double beta) {
   const long double f = expm1l(lg);
   // a relative margin for the evaluation of the bound itself
   return (double)((long double)norm_a * (long double)norm_b * f * (1.0L + ldexpl(1.0L, -20)));
+}
+
+uint64_t gold_mul(uint64_t a, uint64_t b) {
+  return (uint64_t)(((unsigned __int128)a * b) % kGoldP);
+}
+
+uint64_t gold_pow(uint64_t a, uint64_t e) {
+  uint64_t r = 1;
+  a %= kGoldP;
+  while (e) {
+    if (e & 1) r = gold_mul(r, a);
+    a = gold_mul(a, a);
+    e >>= 1;
+  }
+  return r;
+}
+
+uint64_t gold_inv(uint64_t a) { return gold_pow(a, kGoldP - 2); }
+
+uint64_t gold_root(int64_t M) {
+  const uint64_t w32 = gold_pow(7, (kGoldP - 1) >> 32);   // primitive 2^32-th root
+  return gold_pow(w32, (uint64_t(1) << 32) / (uint64_t)M);
+}
+
+void gen_ntt_tables(uint64_t* tw, uint64_t* r16, uint64_t* split) {
+  const int radices[4] = {2, 4, 8, 16};
+  const int spans[4] = {1, 16, 256, 4096};
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const int R = radices[a], Ns = spans[b];
+      const uint64_t w = gold_root((int64_t)R * Ns), wi = gold_inv(w);
+      uint64_t* f = tw + ntt_tw_offset(R, Ns);
+      uint64_t* g = tw + kNttTwEntries + ntt_tw_offset(R, Ns);
+      for (int k = 0; k < Ns; ++k)
+        for (int r = 1; r < R; ++r) {
+          f[k * (R - 1) + (r - 1)] = gold_pow(w, (uint64_t)r * k);
+          g[k * (R - 1) + (r - 1)] = gold_pow(wi, (uint64_t)r * k);
+        }
+    }
+  const uint64_t w16 = gold_root(16), w16i = gold_inv(w16);
+  for (int m = 0; m < 16; ++m) {
+    r16[m] = gold_pow(w16, m);
+    r16[16 + m] = gold_pow(w16i, m);
+  }
+  const uint64_t ws = gold_root(kNttSplitN), wsi = gold_inv(ws);
+  uint64_t f = 1, g = 1;
+  for (int s = 0; s < kNttSplitEntries; ++s) {
+    split[s] = f;
+    split[kNttSplitEntries + s] = g;
+    f = gold_mul(f, ws);
+    g = gold_mul(g, wsi);
+  }
 }
 
 }  // namespace hmv

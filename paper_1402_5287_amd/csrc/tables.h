@@ -23,4 +23,18 @@ double gen_fft_tables(double* tw, double* rtw);
 // like 1 + 2^-53 are not lost.
 double fft_conv_bound(double norm_a, double norm_b, int k, double beta);
 
+// ---------------------------------------------------------------- mod p
+// Arithmetic modulo p = 2^64 - 2^32 + 1 on the host (reference for tables).
+uint64_t gold_mul(uint64_t a, uint64_t b);
+uint64_t gold_pow(uint64_t a, uint64_t e);
+uint64_t gold_inv(uint64_t a);
+// w_M = g^((p-1)/M) with M a power of two <= 2^32, taken as a power of one
+// primitive 2^32-th root so that all sizes are consistent (g = 7 generates
+// the multiplicative group).
+uint64_t gold_root(int64_t M);
+// Fill the NTT tables: forward and inverse (R, Ns) tables (2 kNttTwEntries),
+// the 16 internal roots forward then inverse (32), the split roots forward
+// then inverse (2 kNttSplitEntries).
+void gen_ntt_tables(uint64_t* tw, uint64_t* r16, uint64_t* split);
+
 }  // namespace hmv
