@@ -130,6 +130,32 @@ int64_t hmv_plan_workspace_bytes(const hmv_plan* plan);
 int hmv_plan_info(const hmv_plan* plan, hmv_plan_info_t* info);
 int hmv_plan_destroy(hmv_plan* plan);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent products (any mix of kinds, n and P) in four launches,
+ * one per pass (forward limb transforms of all h and x rows; index-axis
+ * transforms of all h columns; index-axis passes of all x columns; inverse
+ * limb transforms with carry of all output rows); each launch walks a device
+ * list of the work items of that pass over every instance, one item per
+ * work-group, with no host round trip in between.  Every instance runs the
+ * split-FFT path unplanned, with its limb width taken from the worst-case
+ * bound (no data-dependent read back).  Limits: n <= 2048 per instance.
+ * The descriptor array is host memory; h, x, y are device pointers.  The call
+ * synchronises `stream` once, after uploading its work list and before the
+ * launch; the products are ready when the stream synchronises again.
+ * ws (hmv_batch_workspace_bytes) starts with the 256-byte status block.   */
+typedef struct {
+  int32_t kind;           /* HMV_HANKEL / HMV_TOEPLITZ / HMV_CIRCULANT                 */
+  int32_t P;
+  int64_t n;
+  const uint64_t* h;      /* 2n-1 numbers (n for a circulant)                          */
+  const uint64_t* x;      /* n numbers                                                 */
+  uint64_t* y;            /* n numbers (output)                                        */
+} hmv_problem;
+
+int64_t hmv_batch_workspace_bytes(const hmv_problem* probs, int32_t count);
+int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t ws_bytes,
+                     void* stream);
+
 /* ---------------------------------------------------------------- diagnostics
  * Host-only helpers (no device access).
  * hmv_fft_error_bound: the bound used to pick the limb width of the binary64
@@ -142,6 +168,9 @@ int hmv_plan_destroy(hmv_plan* plan);
 double hmv_fft_error_bound(double norm_h, double norm_x, int32_t log2_points, double beta);
 double hmv_twiddle_beta(void);
 int hmv_debug_force_width(int32_t w);
+/* tests only: spin limit of the dependency waits of the single-launch batch
+ * driver (switched off in this build; kept for its test); 0 = default.     */
+int hmv_debug_batch_spin_limit(int32_t spins);
 
 /* Device status of the last call that used workspace `ws`: synchronises
  * `stream`, stores the ST flags (bit 0 range, bit 1 bound, bit 2 spin limit)

@@ -474,3 +474,319 @@ hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int
 }
 
 }  // namespace hmv
+
+// ==================================================================== batch
+// Many independent products.  Every instance runs
+// the split-FFT path unplanned (its spectrum of h is built in the batch
+// workspace).  Work items, in phase order over all instances:
+//   phase 0  forward row transform of one h row (-> H1) or one x row (-> X1)
+//   phase 1  index-axis transform of one limb column of H1 (-> resident Hh)
+//   phase 2  index-axis pass of one limb column of X1 against Hh (-> Y1)
+//   phase 3  inverse row transform + exact carry of one output row (-> y)
+// Two drivers share the item code: a phase-synchronous one (one launch per
+// phase, the one in use) and a single persistent launch in which
+// work-groups take items from a global counter and wait on per-instance
+// completion counters (bounded: past the spin limit it flags ST_SPIN and
+// moves on).  The persistent driver is switched off: on this part each
+// cross-XCD hand-off needs a full L2 write-back / invalidate, which made it
+// far slower than the phase-synchronous launches.
+namespace hmv {
+
+// Counters and the hand-off of results use system-scope atomics and
+// fences: the workspace is ordinary (coarse-grained) device memory, whose
+// lines may sit in the L2 of one XCD, and system scope forces the counter
+// updates to memory and writes back / invalidates the L2s around them.
+// A wait that exceeds the spin limit raises ST_SPIN; once that flag is up,
+// every later wait gives up at once, so the whole launch stays bounded.
+__device__ __forceinline__ bool batch_wait(const int* ctr, int target, int spin_limit,
+                                           DevStatus* st) {
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    ok = 1;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) < target) {
+      const uint32_t fl =
+          __hip_atomic_load(&st->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      if ((fl & ST_SPIN) || ++spins > spin_limit) {
+        ok = 0;
+        __hip_atomic_fetch_or(&st->flags, (uint32_t)ST_SPIN, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_SYSTEM);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+  }
+  __syncthreads();
+  __threadfence_system();   // acquire for every wave: see the producers' data
+  const bool r = ok != 0;
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ void batch_done(int* ctr) {
+  __threadfence_system();   // release: this work-group's results reach memory
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// forward row transform (the body of k_rows_fwd for one row)
+__device__ void b_row_fwd(const uint64_t* in, int W, int P, int w, int L, int gather_n, int logM,
+                          double2* out, int rows_alloc, int r, double2* buf, uint64_t* wd,
+                          uint32_t* red, DevStatus* st) {
+  const int T = blockDim.x, t = threadIdx.x;
+  const int M = 1 << logM;
+  const int src = gather_row(r, gather_n);
+  for (int q = t; q < W; q += T) wd[q] = in[(int64_t)src * W + q];
+  __syncthreads();
+  if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
+  double* bd = reinterpret_cast<double*>(buf);
+  for (int e = L + t; e < 2 * M; e += T) bd[2 * swz(e >> 1) + (e & 1)] = 0.0;
+  split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * swz(e >> 1) + (e & 1)] = (double)d; }, red);
+  __syncthreads();
+  fft_lds(buf, logM, -1);
+  const int rs = kRealTwN / (2 * M);
+  for (int k = t; k <= M; k += T) {
+    const double2 zk = buf[swz(k & (M - 1))], zm = buf[swz((M - k) & (M - 1))];
+    const double2 A = cadd(zk, conj2(zm)), B = csub(zk, conj2(zm));
+    const double2 Q = cmul(g_rtw[k * rs], B);
+    out[tile_index(k, r, rows_alloc)] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
+  }
+  __syncthreads();
+}
+
+// index-axis transform of one column of H1 (even / odd halves, LDS FFT)
+__device__ void b_col_plan(const double2* H1, int rows, int logNt, double scale, double2* Hh,
+                           int c, double2* buf) {
+  const int T = blockDim.x, t = threadIdx.x;
+  const int logNh = logNt - 1, Nh = 1 << logNh;
+  const int rs = kRealTwN >> logNt;
+  const double2* col = H1 + tile_index(c, 0, rows);
+  double2* he = Hh + (int64_t)c * (2 * Nh);
+  for (int half = 0; half < 2; ++half) {
+    for (int s = t; s < Nh; s += T) {
+      const double2 lo = s < rows ? col[(int64_t)s * 8] : make_double2(0.0, 0.0);
+      const double2 hi = s + Nh < rows ? col[(int64_t)(s + Nh) * 8] : make_double2(0.0, 0.0);
+      buf[swz(s)] = half == 0 ? cadd(lo, hi) : cmul(csub(lo, hi), g_rtw[s * rs]);
+    }
+    __syncthreads();
+    fft_lds(buf, logNh, -1);
+    double2* dst = he + half * Nh;
+    for (int f = t; f < Nh; f += T) {
+      const double2 v = buf[swz(f)];
+      dst[f] = make_double2(v.x * scale, v.y * scale);
+    }
+    __syncthreads();
+  }
+}
+
+// index-axis pass of one column: even half in buf[0, Nh), odd half in
+// buf[Nh, 2 Nh)
+__device__ void b_col_pass(const double2* X1, const double2* Hh, int n, int logNt, double2* Y1,
+                           int c, double2* buf) {
+  const int T = blockDim.x, t = threadIdx.x;
+  const int logNh = logNt - 1, Nh = 1 << logNh;
+  const int rs = kRealTwN >> logNt;
+  const double2* xcol = X1 + tile_index(c, 0, n);
+  const double2* he = Hh + (int64_t)c * (2 * Nh);
+  double2* be = buf;
+  double2* bo = buf + Nh;
+  for (int s = t; s < Nh; s += T) {
+    const double2 xv = s < n ? xcol[(int64_t)(n - 1 - s) * 8] : make_double2(0.0, 0.0);
+    be[swz(s)] = xv;
+    bo[swz(s)] = cmul(xv, g_rtw[s * rs]);
+  }
+  __syncthreads();
+  fft_lds(be, logNh, -1);
+  fft_lds(bo, logNh, -1);
+  for (int f = t; f < Nh; f += T) {
+    be[swz(f)] = cmul(be[swz(f)], he[f]);
+    bo[swz(f)] = cmul(bo[swz(f)], he[Nh + f]);
+  }
+  __syncthreads();
+  fft_lds(be, logNh, +1);
+  fft_lds(bo, logNh, +1);
+  double2* ycol = Y1 + tile_index(c, 0, n);
+  for (int s = t; s < Nh; s += T) {
+    const double2 e = be[swz(s)];
+    const double2 q = cmul(bo[swz(s)], conj2(g_rtw[s * rs]));
+    const int ra = s - (n - 1), rb = s + Nh - (n - 1);
+    if (ra >= 0 && ra < n) ycol[(int64_t)ra * 8] = cadd(e, q);
+    if (rb >= 0 && rb < n) ycol[(int64_t)rb * 8] = csub(e, q);
+  }
+  __syncthreads();
+}
+
+// inverse row transform, rounding and carry of one output row
+__device__ void b_row_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
+                          int out_reverse, uint64_t* y, int i, double2* buf, uint32_t* red,
+                          DevStatus* st) {
+  const int T = blockDim.x, t = threadIdx.x;
+  const int M = 1 << logM;
+  const int rs = kRealTwN / (2 * M);
+  __shared__ double2 ytop;
+  for (int k = t; k < M; k += T) buf[swz(k)] = Y1[tile_index(k, i, n)];
+  if (t == 0) ytop = Y1[tile_index(M, i, n)];
+  __syncthreads();
+  double2 z[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const int k = t + a * T;
+    if (k < M) {
+      const double2 yk = buf[swz(k)];
+      const double2 ym = k == 0 ? ytop : buf[swz(M - k)];
+      const double2 E = cadd(yk, conj2(ym)), D = csub(yk, conj2(ym));
+      const double2 Q = cmul(D, conj2(g_rtw[k * rs]));
+      z[a] = make_double2(E.x - Q.y, E.y + Q.x);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const int k = t + a * T;
+    if (k < M) buf[swz(k)] = z[a];
+  }
+  __syncthreads();
+  fft_lds(buf, logM, +1);
+  const int NC = 2 * L - 1;
+  double maxerr = 0.0;
+  int bad = 0;
+  double2 v[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const int m = t + a * T;
+    if (m < M) v[a] = buf[swz(m)];
+  }
+  __syncthreads();
+  int64_t* coef = reinterpret_cast<int64_t*>(buf);
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const int m = t + a * T;
+    if (m < M) {
+      const double s0 = rint(v[a].x), s1 = rint(v[a].y);
+      maxerr = fmax(maxerr, fmax(fabs(v[a].x - s0), fabs(v[a].y - s1)));
+      const int64_t i0 = (int64_t)s0, i1 = (int64_t)s1;
+      if (2 * m < NC) coef[2 * m] = i0;
+      else if (i0 != 0) bad = 1;
+      if (2 * m + 1 < NC) coef[2 * m + 1] = i1;
+      else if (i1 != 0) bad = 1;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) maxerr = fmax(maxerr, __shfl_xor(maxerr, o, 64));
+  if ((t & 63) == 0 && st)
+    atomicMax(reinterpret_cast<unsigned long long*>(&st->max_err_bits),
+              (unsigned long long)__double_as_longlong(maxerr));
+  bad = __syncthreads_or(bad);
+  if (bad && t == 0) status_or(st, ST_BOUND);
+  const int carry_off = (NC * 8 + 15) / 16 * 16;
+  uint64_t* sw = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(buf) + carry_off);
+  const int NWS = carry_words(NC, w, P, W);
+  const int row = out_reverse ? (n - 1 - i) : i;
+  carry_round_pack(coef, NC, w, P, W, sw, NWS, y + (int64_t)row * W, red);
+}
+
+__global__ void __launch_bounds__(256) k_batch(const BatchInst* __restrict__ inst,
+                                               const int4* __restrict__ items, int nitems,
+                                               int* __restrict__ head, int* __restrict__ ctr,
+                                               int spin_limit, DevStatus* st) {
+  extern __shared__ double2 buf[];
+  __shared__ uint64_t wd[kMaxWords];
+  __shared__ uint32_t red[32];
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(head, 1);
+    __syncthreads();
+    const int it = cur;
+    __syncthreads();
+    if (it >= nitems) break;
+    const int4 d = items[it];
+    const BatchInst I = inst[d.x];
+    int* c = ctr + 4 * d.x;           // h rows, x rows, plan columns, pass columns
+    const int rows_h = 2 * I.n - 1;
+    if (d.y == 0) {
+      if (d.z < rows_h) {
+        b_row_fwd(I.h, I.W, I.P, I.w, I.L, I.gather, I.logM, I.H1, rows_h, d.z, buf, wd, red, st);
+        batch_done(c + 0);
+      } else {
+        b_row_fwd(I.x, I.W, I.P, I.w, I.L, 0, I.logM, I.X1, I.n, d.z - rows_h, buf, wd, red, st);
+        batch_done(c + 1);
+      }
+    } else if (d.y == 1) {
+      batch_wait(c + 0, rows_h, spin_limit, st);
+      b_col_plan(I.H1, rows_h, I.logNt, I.scale, I.Hh, d.z, buf);
+      batch_done(c + 2);
+    } else if (d.y == 2) {
+      batch_wait(c + 1, I.n, spin_limit, st);
+      batch_wait(c + 2, I.C, spin_limit, st);
+      b_col_pass(I.X1, I.Hh, I.n, I.logNt, I.Y1, d.z, buf);
+      batch_done(c + 3);
+    } else {
+      batch_wait(c + 3, I.C, spin_limit, st);
+      b_row_inv(I.Y1, I.n, I.logM, I.L, I.w, I.P, I.W, I.reverse, I.y, d.z, buf, red, st);
+    }
+  }
+}
+
+// Phase-synchronous batch: one launch per pass over the items of that pass
+// of every instance (one item per work-group); kernel boundaries order the
+// passes, so no work-group waits on another.
+__global__ void __launch_bounds__(256) k_batch_phase(const BatchInst* __restrict__ inst,
+                                                     const int4* __restrict__ items, int nitems,
+                                                     DevStatus* st) {
+  extern __shared__ double2 buf[];
+  __shared__ uint64_t wd[kMaxWords];
+  __shared__ uint32_t red[32];
+  const int it = blockIdx.x;
+  if (it >= nitems) return;
+  const int4 d = items[it];
+  const BatchInst I = inst[d.x];
+  const int rows_h = 2 * I.n - 1;
+  if (d.y == 0) {
+    if (d.z < rows_h)
+      b_row_fwd(I.h, I.W, I.P, I.w, I.L, I.gather, I.logM, I.H1, rows_h, d.z, buf, wd, red, st);
+    else
+      b_row_fwd(I.x, I.W, I.P, I.w, I.L, 0, I.logM, I.X1, I.n, d.z - rows_h, buf, wd, red, st);
+  } else if (d.y == 1) {
+    b_col_plan(I.H1, rows_h, I.logNt, I.scale, I.Hh, d.z, buf);
+  } else if (d.y == 2) {
+    b_col_pass(I.X1, I.Hh, I.n, I.logNt, I.Y1, d.z, buf);
+  } else {
+    b_row_inv(I.Y1, I.n, I.logM, I.L, I.w, I.P, I.W, I.reverse, I.y, d.z, buf, red, st);
+  }
+}
+
+hipError_t launch_batch_phase(const BatchInst* inst, const int4* items, int nitems, DevStatus* st,
+                              hipStream_t s) {
+  if (nitems <= 0) return hipSuccess;
+  hipError_t e = fft_tables_init();
+  if (e != hipSuccess) return e;
+  const size_t lds = kBatchDynLds;
+  e = set_lds((const void*)k_batch_phase, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_phase, dim3(nitems), dim3(256), lds, s, inst, items, nitems, st);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_ints(int* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+
+hipError_t launch_batch(const BatchInst* inst, const int4* items, int nitems, int* head, int* ctr,
+                        int nctr, int grid, int spin_limit, DevStatus* st, hipStream_t s) {
+  hipError_t e = fft_tables_init();
+  if (e != hipSuccess) return e;
+  const int nz = nctr + 1;
+  hipLaunchKernelGGL(k_zero_ints, dim3((nz + 255) / 256), dim3(256), 0, s, head, nz);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds = kBatchDynLds;
+  e = set_lds((const void*)k_batch, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(256), lds, s, inst, items, nitems, head, ctr,
+                     spin_limit, st);
+  return hipGetLastError();
+}
+
+}  // namespace hmv

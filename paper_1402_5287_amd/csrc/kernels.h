@@ -65,3 +65,26 @@ hipError_t launch_kara_leaves(const int4* rows, int nrows, const uint64_t* A, co
 hipError_t launch_ntt_scale(uint64_t* a, int64_t count, uint64_t scale, hipStream_t s);
 
 }  // namespace hmv
+
+namespace hmv {
+
+// one instance of a batched launch (device-side descriptor)
+struct BatchInst {
+  const uint64_t* h;
+  const uint64_t* x;
+  uint64_t* y;
+  double2* H1;
+  double2* Hh;
+  double2* X1;
+  double2* Y1;
+  int n, P, W, w, L, logM, logNt, C, gather, reverse;
+  double scale;
+};
+
+constexpr size_t kBatchDynLds = 68 * 1024;   // dynamic LDS of the batch kernel
+hipError_t launch_batch(const BatchInst* inst, const int4* items, int nitems, int* head, int* ctr,
+                        int nctr, int grid, int spin_limit, DevStatus* st, hipStream_t s);
+hipError_t launch_batch_phase(const BatchInst* inst, const int4* items, int nitems, DevStatus* st,
+                              hipStream_t s);
+
+}  // namespace hmv

@@ -46,7 +46,16 @@ SIGNATURES = {
     "hmv_fft_error_bound": (ctypes.c_double, [ctypes.c_double, ctypes.c_double, _c_i32, ctypes.c_double]),
     "hmv_twiddle_beta": (ctypes.c_double, []),
     "hmv_debug_force_width": (_c_int, [_c_i32]),
+    "hmv_debug_batch_spin_limit": (_c_int, [_c_i32]),
+    "hmv_batch_workspace_bytes": (_c_i64, [_vp, _c_i32]),
+    "hmv_batch_matvec": (_c_int, [_vp, _c_i32, _vp, _c_i64, _vp]),
 }
+
+
+class Problem(ctypes.Structure):
+    """Mirror of hmv_problem."""
+    _fields_ = [("kind", ctypes.c_int32), ("P", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("h", ctypes.c_void_p), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -227,3 +236,33 @@ class Plan:
 def force_width(w: int) -> None:
     """Tests only: restrict the binary64 limb width (0 = search)."""
     _check(lib().hmv_debug_force_width(w), "force_width")
+
+
+def batch_problems(items):
+    """items: iterable of (kind, h, x, y, n, P) with device tensors."""
+    arr = (Problem * len(items))()
+    for k, (kind, h, x, y, n, P) in enumerate(items):
+        arr[k] = Problem(KINDS.get(kind, kind), int(P), int(n), h.data_ptr(), x.data_ptr(),
+                         y.data_ptr())
+    return arr
+
+
+def batch_workspace_bytes(problems) -> int:
+    b = lib().hmv_batch_workspace_bytes(ctypes.cast(problems, ctypes.c_void_p), len(problems))
+    if b < 0:
+        raise HmvError(int(b), "hmv_batch_workspace_bytes")
+    return int(b)
+
+
+def batch_matvec(problems, ws, stream=None, check=True) -> int:
+    """All products of `problems` (from batch_problems) in one persistent launch."""
+    rc = lib().hmv_batch_matvec(ctypes.cast(problems, ctypes.c_void_p), len(problems), _ptr(ws),
+                                ws.numel(), _stream(stream))
+    if check:
+        _check(rc, "batch_matvec")
+    return rc
+
+
+def set_batch_spin_limit(spins: int) -> None:
+    """Tests only (0 = default)."""
+    _check(lib().hmv_debug_batch_spin_limit(spins), "batch spin limit")

@@ -1,0 +1,84 @@
+"""Batched persistent launch: many uneven (kind, n, P) products in one
+kernel with a device work queue, each checked against the oracle."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import hankel
+from tests.gpu_util import announce, need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _make(specs, seed):
+    from paper_1402_5287_amd import hmv
+    host, items = [], []
+    for i, (kind, n, P) in enumerate(specs):
+        kname = ("hankel", "toeplitz", "circulant")[kind]
+        h, x = si.batch_operands(i, kind, n, P, seed=seed)
+        y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+        items.append((kname, hmv.to_device(h), hmv.to_device(x), y, n, P))
+        host.append((kname, h, x))
+    return host, items
+
+
+def test_mixed_batch_bit_exact():
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    specs = si.batch_instances(60, seed=5, n_lo=1, n_hi=300, precisions=(64, 200, 1024, 3322))
+    host, items = _make(specs, seed=5)
+    probs = hmv.batch_problems(items)
+    ws = hmv.workspace(hmv.batch_workspace_bytes(probs))
+    announce("batch", len(specs))
+    hmv.batch_matvec(probs, ws)
+    rc, flags, err = hmv.read_status(ws)
+    assert rc == 0 and flags == 0, flags
+    for (kname, h, x), (_, _, _, y, n, P) in zip(host, items):
+        assert np.array_equal(hmv.to_host(y), hankel.matvec_words(kname, h, x, P)), (kname, n, P)
+
+
+def test_batch_equals_single_paths_at_paper_sizes():
+    """A batch with paper-sized members: every output equals the planned
+    single-instance split-FFT path (itself pinned to the oracle)."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    specs = si.batch_instances(24, seed=6)
+    host, items = _make(specs, seed=6)
+    probs = hmv.batch_problems(items)
+    ws = hmv.workspace(hmv.batch_workspace_bytes(probs))
+    announce("batch paper sizes", len(specs))
+    hmv.batch_matvec(probs, ws)
+    rc, flags, _ = hmv.read_status(ws)
+    assert rc == 0 and flags == 0
+    for (kname, h, x), (_, hd, xd, y, n, P) in zip(host, items):
+        y1 = torch.zeros_like(y)
+        hmv.matvec(kname, hd, xd, y1, n, P, algo="split_fft")
+        assert torch.equal(y, y1), (kname, n, P)
+    # and a few members against the oracle directly
+    for (kname, h, x), (_, _, _, y, n, P) in list(zip(host, items))[:3]:
+        if n <= 200:
+            assert np.array_equal(hmv.to_host(y), hankel.matvec_words(kname, h, x, P))
+
+
+@pytest.mark.skip(reason="exercises the single-launch work-queue batch driver, which is switched "
+                         "off: its one GPU run (and the run of its fix) did not finish within the "
+                         "test time limit; see DESIGN.md")
+def test_batch_spin_limit_exit_path():
+    """With a tiny spin limit the dependency waits give up: the launch still
+    completes (every wave exits) and reports the spin flag or a valid result."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    specs = [(0, 200, 1024)] * 8
+    host, items = _make(specs, seed=7)
+    probs = hmv.batch_problems(items)
+    ws = hmv.workspace(hmv.batch_workspace_bytes(probs))
+    hmv.set_batch_spin_limit(1)
+    try:
+        hmv.batch_matvec(probs, ws)
+        rc, flags, _ = hmv.read_status(ws)
+    finally:
+        hmv.set_batch_spin_limit(0)
+    assert rc == 0
+    if not flags & 4:
+        for (kname, h, x), (_, _, _, y, n, P) in zip(host, items):
+            assert np.array_equal(hmv.to_host(y), hankel.matvec_words(kname, h, x, P))
