@@ -156,6 +156,38 @@ int64_t hmv_batch_workspace_bytes(const hmv_problem* probs, int32_t count);
 int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t ws_bytes,
                      void* stream);
 
+/* ---------------------------------------------------------------- serving
+ * A request scheduler for sessions of planned matvecs (continuous
+ * batching).  The caller provides one device pool (pool_bytes) from which
+ * the server carves each admitted request's workspace, and registers
+ * resident plans.  A request (one matvec of a session) is admitted onto a
+ * free stream slot as soon as the pool can hold its workspace; requests of
+ * different sessions then overlap on the device, and requests submitted
+ * while others run are admitted as slots and memory free up.  Requests of
+ * one session run in submission order.  Admission is oldest-first with a
+ * reservation for the oldest request that is waiting for memory.
+ * hmv_server_submit enqueues and admits what fits (asynchronous);
+ * hmv_server_poll retires finished requests (ids and their device status
+ * flags, or a negative hmv_status) and admits waiting ones.  x and y must
+ * stay valid until their request is retired.  The server creates its own
+ * default-priority streams and events; destroy synchronises them.  One
+ * thread at a time may call into a server.                                  */
+typedef struct hmv_server hmv_server;
+
+typedef struct {
+  int64_t in_flight, waiting, admitted, completed, max_in_flight;
+  int64_t pool_used, pool_peak, pool_bytes;
+} hmv_server_stats_t;
+
+int hmv_server_create(hmv_server** out, void* pool, int64_t pool_bytes, int32_t max_slots);
+int hmv_server_add_plan(hmv_server* server, const hmv_plan* plan, int32_t* matrix_id);
+int hmv_server_submit(hmv_server* server, int32_t matrix_id, int64_t session, const uint64_t* x,
+                      uint64_t* y, int64_t* request_id);
+int hmv_server_poll(hmv_server* server, int64_t* done_ids, int32_t* done_status, int32_t cap,
+                    int32_t* n_done);
+int hmv_server_stats(const hmv_server* server, hmv_server_stats_t* stats);
+int hmv_server_destroy(hmv_server* server);
+
 /* ---------------------------------------------------------------- diagnostics
  * Host-only helpers (no device access).
  * hmv_fft_error_bound: the bound used to pick the limb width of the binary64

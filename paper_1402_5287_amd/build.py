@@ -20,7 +20,8 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhmv.so")
 
 SOURCES = ["api.cpp", "plan.cpp", "tables.cpp", "status.hip", "school.hip", "fftpath.hip",
-           "nttpath.hip", "batch.cpp"]
+           "nttpath.hip", "batch.cpp",
+           "serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

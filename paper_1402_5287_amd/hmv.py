@@ -49,7 +49,21 @@ SIGNATURES = {
     "hmv_debug_batch_spin_limit": (_c_int, [_c_i32]),
     "hmv_batch_workspace_bytes": (_c_i64, [_vp, _c_i32]),
     "hmv_batch_matvec": (_c_int, [_vp, _c_i32, _vp, _c_i64, _vp]),
+    "hmv_server_create": (_c_int, [ctypes.POINTER(_vp), _vp, _c_i64, _c_i32]),
+    "hmv_server_add_plan": (_c_int, [_vp, _vp, ctypes.POINTER(_c_i32)]),
+    "hmv_server_submit": (_c_int, [_vp, _c_i32, _c_i64, _vp, _vp, ctypes.POINTER(_c_i64)]),
+    "hmv_server_poll": (_c_int, [_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i32), _c_i32,
+                                 ctypes.POINTER(_c_i32)]),
+    "hmv_server_stats": (_c_int, [_vp, _vp]),
+    "hmv_server_destroy": (_c_int, [_vp]),
 }
+
+
+class ServerStats(ctypes.Structure):
+    """Mirror of hmv_server_stats_t."""
+    _fields_ = [(f, ctypes.c_int64) for f in ("in_flight", "waiting", "admitted", "completed",
+                                              "max_in_flight", "pool_used", "pool_peak",
+                                              "pool_bytes")]
 
 
 class Problem(ctypes.Structure):
@@ -266,3 +280,51 @@ def batch_matvec(problems, ws, stream=None, check=True) -> int:
 def set_batch_spin_limit(spins: int) -> None:
     """Tests only (0 = default)."""
     _check(lib().hmv_debug_batch_spin_limit(spins), "batch spin limit")
+
+
+class Server:
+    """Continuous-batching request scheduler (hmv_server_*) over one pool."""
+
+    def __init__(self, pool_bytes: int, slots: int = 8, device="cuda"):
+        import torch
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p(0)
+        _check(lib().hmv_server_create(ctypes.byref(h), _ptr(self.pool), self.pool.numel(), slots),
+               "server_create")
+        self.handle = h
+        self.plans = []
+
+    def add_plan(self, plan: "Plan") -> int:
+        mid = _c_i32(0)
+        _check(lib().hmv_server_add_plan(self.handle, plan.handle, ctypes.byref(mid)), "add_plan")
+        self.plans.append(plan)
+        return int(mid.value)
+
+    def submit(self, matrix_id: int, session: int, x, y) -> int:
+        rid = _c_i64(0)
+        _check(lib().hmv_server_submit(self.handle, matrix_id, session, _ptr(x), _ptr(y),
+                                       ctypes.byref(rid)), "submit")
+        return int(rid.value)
+
+    def poll(self, cap: int = 64):
+        ids = (_c_i64 * cap)()
+        sts = (_c_i32 * cap)()
+        nd = _c_i32(0)
+        _check(lib().hmv_server_poll(self.handle, ids, sts, cap, ctypes.byref(nd)), "poll")
+        return [(int(ids[k]), int(sts[k])) for k in range(nd.value)]
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().hmv_server_stats(self.handle, ctypes.byref(st)), "stats")
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hmv_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

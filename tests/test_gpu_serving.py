@@ -1,0 +1,73 @@
+"""Request scheduler (continuous batching of Lanczos-shaped sessions): every
+result of the mixed run equals the same request run alone."""
+import random
+
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import hankel
+from tests.gpu_util import announce, need_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def test_mixed_sessions_equal_alone():
+    need_gpu()
+    from paper_1402_5287_amd import hmv, serving
+    mats = [("hankel", 64, 3322), ("toeplitz", 300, 1024), ("circulant", 1000, 3322),
+            ("hankel", 700, 700)]
+    plans, host_h = [], []
+    for i, (kind, n, P) in enumerate(mats):
+        hl = n if kind == "circulant" else 2 * n - 1
+        h = si.uniform(hl, P, (90, i))
+        host_h.append(h)
+        plans.append(hmv.Plan(kind, hmv.to_device(h), n, P, algo="auto"))
+    biggest = max(p.mv_ws_bytes for p in plans)
+    # a pool that holds about two of the largest workspaces: admission must wait
+    server = hmv.Server(pool_bytes=int(2.3 * biggest), slots=4)
+    mids = [server.add_plan(p) for p in plans]
+    rng = random.Random(3)
+    sessions, host_x = [], {}
+    arr = serving.poisson_arrivals(400.0, 10, rng)
+    for sid in range(10):
+        m = rng.randrange(len(mats))
+        kind, n, P = mats[m]
+        xs, ys = [], []
+        for k in range(rng.randint(3, 8)):
+            x = si.uniform(n, P, (91, sid, k))
+            host_x[(sid, k)] = x
+            xs.append(hmv.to_device(x))
+            ys.append(torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda"))
+        sessions.append(serving.Session(sid=sid, matrix_id=mids[m], arrival=arr[sid], xs=xs, ys=ys))
+    announce("serving", len(sessions))
+    wall, lats, recs = serving.run(server, sessions, time_limit=120.0)
+    torch.cuda.synchronize()
+    st = server.stats()
+    assert st["completed"] == sum(len(s.xs) for s in sessions)
+    assert st["max_in_flight"] >= 2
+    assert all(status == 0 for (_, _, _, status) in recs)
+    for s in sessions:
+        m = mids.index(s.matrix_id)
+        kind, n, P = mats[m]
+        for k, (x, y) in enumerate(zip(s.xs, s.ys)):
+            alone = torch.zeros_like(y)
+            plans[m].matvec(x, alone, ws=plans[m].new_workspace())
+            torch.cuda.synchronize()
+            assert torch.equal(alone, y), (s.sid, k)
+            if n <= 300:
+                want = hankel.matvec_words(kind, host_h[m], host_x[(s.sid, k)], P)
+                assert np.array_equal(hmv.to_host(y), want)
+    server.close()
+
+
+def test_pool_too_small_is_refused():
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    n, P = 500, 3322
+    plan = hmv.Plan("hankel", hmv.to_device(si.uniform(2 * n - 1, P, (92,))), n, P)
+    server = hmv.Server(pool_bytes=plan.mv_ws_bytes // 2, slots=2)
+    with pytest.raises(hmv.HmvError) as ei:
+        server.add_plan(plan)
+    assert ei.value.code == hmv.ENOMEM
+    server.close()
