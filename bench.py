@@ -14,6 +14,11 @@ dominant kernel (from HIP events recorded around each kernel on its stream),
 the replay rate of a HIP graph of one step, the exact GPU schoolbook on the
 same operands (speedup), and the CPU oracle (Python-int schoolbook) timed on
 a bounded row sample on the host cores.
+
+Three further sections report the other workloads of the method (each can be
+switched off): the four exact paths on one n = 1024 Hilbert-type product,
+the batched launch of 256 uneven products, and the request scheduler under
+Poisson arrivals of closed-loop sessions on eight resident matrices.
 """
 from __future__ import annotations
 
@@ -21,6 +26,7 @@ import argparse
 import hashlib
 import json
 import os
+import random
 import statistics
 import sys
 import time
@@ -79,6 +85,14 @@ def main():
     ap.add_argument("--no-school", action="store_true", help="skip the GPU schoolbook comparison")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-verify", action="store_true", help="skip the GMP full-vector check")
+    ap.add_argument("--no-paths", action="store_true", help="skip the n=1024 four-path section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch section")
+    ap.add_argument("--no-serving", action="store_true", help="skip the scheduler section")
+    ap.add_argument("--serving-sessions", type=int, default=24)
+    ap.add_argument("--serving-loads", default="0.7",
+                    help="comma-separated offered loads, as fractions of saturated throughput")
+    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-pool-gb", type=float, default=4.5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run a plain device copy of BYTES bytes (5 times), the reference "
                          "for scaling hardware byte counters")
@@ -86,7 +100,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md and not built.", file=sys.stderr)
+              "a multi-GPU layout is not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -282,8 +296,231 @@ def main():
         "max_round_err": max_err,
         "roofline": roofline, "kernels": path, "graph": graph, "schoolbook_gpu": school,
         "verify": verify, "cpu_baseline": cpu,
+        "paths_n1024": None if args.no_paths else section_paths(dev),
+        "batch": None if args.no_batch else section_batch(dev),
+        "serving": None if args.no_serving else section_serving(dev, procs, args),
     }
     print(json.dumps(out), flush=True)
+
+
+def _ms_between(e0, e1):
+    return e0.elapsed_time(e1)
+
+
+def section_paths(dev, reps=5):
+    """Four exact paths on the n = 1024, P = 33220 Hilbert-type product; every
+    result must equal every other and the exact CPU product."""
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_1402_5287_amd import hmv
+    n, P = 1024, 33220
+    h, x = si.hilbert_case(n, P)
+    hd, xd = hmv.to_device(h, dev), hmv.to_device(x, dev)
+    res, outs = {}, {}
+    for algo in ("split_fft", "ntt", "karatsuba"):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        plan = hmv.Plan("hankel", hd, n, P, algo=algo)
+        e[1].record()
+        y = torch.zeros_like(xd)
+        plan.matvec(xd, y)
+        torch.cuda.synchronize()
+        e[2].record()
+        for _ in range(reps):
+            plan.matvec(xd, y)
+        e[3].record()
+        torch.cuda.synchronize()
+        info = plan.info()
+        res[algo] = {"plan_ms": round(_ms_between(e[0], e[1]), 3),
+                     "matvec_ms": round(_ms_between(e[2], e[3]) / reps, 4),
+                     "w": info["w"], "L": info["L"], "Nt": info["Nt"], "Nz": info["Nz"]}
+        outs[algo] = y
+        plan.close()
+        log(f"paths n=1024 {algo}: {res[algo]}")
+    ys = torch.zeros_like(xd)
+    ws = hmv.workspace(hmv.oneshot_workspace_bytes("hankel", n, P, "schoolbook"), device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    hmv.matvec("hankel", hd, xd, ys, n, P, algo="schoolbook", ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    res["schoolbook"] = {"matvec_ms": round(_ms_between(e0, e1), 3)}
+    log(f"paths n=1024 schoolbook: {res['schoolbook']}")
+    outs["schoolbook"] = ys
+    equal = all(torch.equal(outs[a], ys) for a in outs)
+    res["all_equal"] = bool(equal)
+    from oracle import kronecker
+    if kronecker.available():
+        res["equal_exact_cpu"] = bool(np.array_equal(hmv.to_host(ys),
+                                                     kronecker.hankel_matvec_words(h, x, P)))
+    if not equal or not res.get("equal_exact_cpu", True):
+        raise SystemExit(f"n=1024 paths disagree: {res}")
+    sb = res["schoolbook"]["matvec_ms"]
+    for a in ("split_fft", "ntt", "karatsuba"):
+        res[a]["speedup_vs_schoolbook"] = round(sb / res[a]["matvec_ms"], 1)
+    return res
+
+
+def section_batch(dev, count=256, reps=3):
+    """256 uneven (kind, n, P) products in the batched launch, checked against
+    the single-product path one by one."""
+    import torch
+
+    import seeded_inputs as si
+    from paper_1402_5287_amd import hmv
+    t = time.time()
+    inst = si.batch_instances(count)
+    items, hs, xs = [], [], []
+    for i, (kind, n, P) in enumerate(inst):
+        h, x = si.batch_operands(i, kind, n, P)
+        hd, xd = hmv.to_device(h, dev), hmv.to_device(x, dev)
+        yd = torch.zeros_like(xd)
+        items.append((kind, hd, xd, yd, n, P))
+    log(f"batch: {count} instances generated in {time.time() - t:.1f}s")
+    probs = hmv.batch_problems(items)
+    ws = hmv.workspace(hmv.batch_workspace_bytes(probs), device=dev)
+    hmv.batch_matvec(probs, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        hmv.batch_matvec(probs, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    bms = _ms_between(e0, e1) / reps
+    # the same products one at a time (one-shot auto path), timed and compared
+    single_ws = hmv.workspace(max(hmv.oneshot_workspace_bytes(k, n, P) for (k, _, _, _, n, P)
+                                  in items), device=dev)
+    outs = []
+    e0.record()
+    for (kind, hd, xd, yd, n, P) in items:
+        y1 = torch.zeros_like(yd)
+        hmv.matvec(kind, hd, xd, y1, n, P, ws=single_ws)
+        outs.append(y1)
+    e1.record()
+    torch.cuda.synchronize()
+    sms = _ms_between(e0, e1)
+    equal = all(torch.equal(o, it[3]) for o, it in zip(outs, items))
+    rc, flags, _ = hmv.read_status(ws)
+    res = {"instances": count, "launches": 4, "batch_ms": round(bms, 3),
+           "products_per_s": round(count / (bms * 1e-3), 1),
+           "one_by_one_ms": round(sms, 3), "equal_to_single_path": bool(equal),
+           "status_flags": flags,
+           "kinds": [sum(1 for k, _, _ in inst if k == c) for c in range(3)],
+           "workspace_mb": round(ws.numel() / 2**20, 1)}
+    log(f"batch: {res}")
+    if not equal or flags:
+        raise SystemExit("batched products differ from the single path")
+    return res
+
+
+def _serve_vectors(args):
+    import seeded_inputs as si
+    m, n, P, j = args
+    return si.serving_x(m, n, P, j)
+
+
+def section_serving(dev, procs, args, pool_vectors=4):
+    """Poisson arrivals of closed-loop sessions on 8 resident matrices through
+    the request scheduler: matvecs/s and request latency p50/p99."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    import seeded_inputs as si
+    from paper_1402_5287_amd import hmv, serving
+    t = time.time()
+    mats = si.serving_matrices()
+    plans = []
+    for m, (n, P) in enumerate(mats):
+        plans.append(hmv.Plan("hankel", hmv.to_device(si.serving_h(m, n, P), dev), n, P))
+    jobs = [(m, n, P, j) for m, (n, P) in enumerate(mats) for j in range(pool_vectors)]
+    with mp.get_context("fork").Pool(procs) as pool:
+        vecs = pool.map(_serve_vectors, jobs)
+    xpool = {}
+    for (m, n, P, j), v in zip(jobs, vecs):
+        xpool[(m, j)] = hmv.to_device(v, dev)
+    torch.cuda.synchronize()
+    log(f"serving: {len(mats)} plans + {len(jobs)} vectors ready in {time.time() - t:.1f}s")
+    W = hmv.words(mats[0][1])
+    ws_need = [p.mv_ws_bytes for p in plans]
+    pool_bytes = int(args.serving_pool_gb * 2**30)
+    info = [p.info() for p in plans]
+
+    def make_sessions(desc, arrivals, base):
+        out = []
+        for sid, ((m, length), arr) in enumerate(zip(desc, arrivals)):
+            n = mats[m][0]
+            y = torch.zeros((n, W), dtype=torch.int64, device=dev)
+            xs = [xpool[(m, (sid + k) % pool_vectors)] for k in range(length)]
+            out.append(serving.Session(sid=base + sid, matrix_id=m, arrival=arr, xs=xs,
+                                       ys=[y] * length))
+        return out
+
+    def drive(sessions):
+        server = hmv.Server(pool_bytes, slots=args.serving_slots, device=dev)
+        for p in plans:
+            server.add_plan(p)
+        wall, lats, recs = serving.run(server, sessions, time_limit=300.0)
+        torch.cuda.synchronize()
+        st = server.stats()
+        server.close()
+        if any(r[3] != 0 for r in recs):
+            raise SystemExit("serving: a request reported a nonzero status")
+        return wall, lats, st
+
+    # saturated throughput: every session present at t = 0
+    sat_desc = [(m % len(mats), 30) for m in range(2 * len(mats))]
+    sat = make_sessions(sat_desc, [0.0] * len(sat_desc), 0)
+    wall, lats, st = drive(sat)
+    sat_rate = sum(len(s.xs) for s in sat) / wall
+    log(f"serving: saturated {sat_rate:.1f} matvecs/s ({wall:.2f}s, max in flight "
+        f"{st['max_in_flight']})")
+    res = {"matrices": [{"n": n, "P": P, "w": i["w"], "Nt": i["Nt"], "Nz": i["Nz"],
+                         "workspace_mb": round(b / 2**20, 1)}
+                        for (n, P), i, b in zip(mats, info, ws_need)],
+           "slots": args.serving_slots, "pool_gb": args.serving_pool_gb,
+           "saturated_matvecs_per_s": round(sat_rate, 1), "loads": []}
+    for li, load in enumerate(float(v) for v in args.serving_loads.split(",")):
+        desc = si.serving_sessions(args.serving_sessions, len(mats), seed=li)
+        mean_len = sum(d[1] for d in desc) / len(desc)
+        lam = load * sat_rate / mean_len
+        arrivals = serving.poisson_arrivals(lam, len(desc), random.Random(1000 + li))
+        sess = make_sessions(desc, arrivals, 10000 * (li + 1))
+        wall, lats, st = drive(sess)
+        total = sum(len(s.xs) for s in sess)
+        by_n = {}
+        for s in sess:
+            by_n.setdefault(mats[s.matrix_id][0], []).extend(s.latencies)
+        # every session's last result against the same product run alone
+        same = True
+        for s in sess:
+            p = plans[s.matrix_id]
+            alone = torch.zeros_like(s.ys[-1])
+            p.matvec(s.xs[-1], alone, ws=p.new_workspace())
+            torch.cuda.synchronize()
+            same = same and bool(torch.equal(alone, s.ys[-1]))
+        ent = {"load": load, "sessions": len(sess), "arrival_rate_per_s": round(lam, 3),
+               "matvecs": total, "wall_s": round(wall, 3),
+               "matvecs_per_s": round(total / wall, 1),
+               "p50_ms": round(1e3 * serving.percentile(lats, 0.5), 3),
+               "p99_ms": round(1e3 * serving.percentile(lats, 0.99), 3),
+               "by_n": {str(n): {"p50_ms": round(1e3 * serving.percentile(v, 0.5), 3),
+                                 "p99_ms": round(1e3 * serving.percentile(v, 0.99), 3),
+                                 "count": len(v)} for n, v in sorted(by_n.items())},
+               "max_in_flight": st["max_in_flight"],
+               "pool_peak_mb": round(st["pool_peak"] / 2**20, 1),
+               "last_results_equal_alone": same}
+        log(f"serving load {load}: {ent}")
+        if not same:
+            raise SystemExit("serving: a result in the mix differs from the same product alone")
+        res["loads"].append(ent)
+    for p in plans:
+        p.close()
+    return res
 
 
 if __name__ == "__main__":

@@ -162,3 +162,26 @@ def batch_instances(count: int = 256, seed: int = 0, n_lo: int = 32, n_hi: int =
 def batch_operands(i: int, kind: int, n: int, P: int, seed: int = 0):
     hlen = n if kind == 2 else 2 * n - 1
     return uniform(hlen, P, (4, 0, seed, i)), uniform(n, P, (4, 1, seed, i))
+
+
+def serving_matrices(sizes=(1000, 2000, 4000, 8000), copies: int = 2, P: int = 33220):
+    """Resident matrices of the serving workload: `copies` Hankel matrices per
+    n.  Returns a list of (n, P); matrix m has h = serving_h(m, n, P)."""
+    return [(n, P) for _ in range(copies) for n in sizes]
+
+
+def serving_h(m: int, n: int, P: int):
+    return uniform(2 * n - 1, P, (5, 0, m))
+
+
+def serving_x(m: int, n: int, P: int, j: int):
+    """j-th vector of the pool of matrix m: uniform, then unit 2-norm."""
+    return unit_norm(uniform(n, P, (5, 1, m, j)), P)
+
+
+def serving_sessions(count: int, n_matrices: int, seed: int = 0, len_lo: int = 50,
+                     len_hi: int = 300):
+    """Session descriptors (matrix index, number of matvecs), drawn uniformly."""
+    rng = _rng((5, 2, seed))
+    return [(int(rng.integers(0, n_matrices)), int(rng.integers(len_lo, len_hi + 1)))
+            for _ in range(count)]
