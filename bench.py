@@ -54,6 +54,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
+KERNEL_NAMES = {"split_fft": ("k_rows_fwd", "k_cols_pass", "k_rows_inv"),
+                "ntt": ("k_ntt_rows_fwd", "k_ntt_cols_pass", "k_ntt_rows_inv")}
+
+
+def kernel_bytes(algo, n, W, info):
+    """Algorithmic HBM bytes of the three kernels of one planned matvec:
+    x words in + X1 spectrum out; X1 in + resident spectrum of h in + Y1 out;
+    Y1 in + y words out.  split_fft keeps the Hermitian half (Nz/2 + 1
+    complex binary64 per row), ntt the full Nz residues (8 bytes each)."""
+    Nt, Nz = info["Nt"], info["Nz"]
+    row = (Nz // 2 + 1) * 16 if algo == "split_fft" else Nz * 8
+    cols = row
+    return (n * W * 8 + n * row, 2 * n * row + Nt * cols, n * row + n * W * 8)
+
+
 def _gen_x(args):
     import seeded_inputs as si
     n, P, k = args
@@ -81,6 +96,10 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--P", type=int, default=33220)
     ap.add_argument("--vectors", type=int, default=200)
+    ap.add_argument("--algo", default="split_fft", choices=("split_fft", "ntt"),
+                    help="path of the timed session (the headline is split_fft)")
+    ap.add_argument("--no-peer", action="store_true",
+                    help="skip timing the NTT path on the same session")
     ap.add_argument("--cpu-rows", type=int, default=16, help="oracle row sample (0 = skip)")
     ap.add_argument("--no-school", action="store_true", help="skip the GPU schoolbook comparison")
     ap.add_argument("--no-graph", action="store_true")
@@ -137,7 +156,7 @@ def main():
     # ---- plan (once per session)
     ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev_a.record()
-    plan = hmv.Plan("hankel", h_dev, n, P, algo="split_fft")
+    plan = hmv.Plan("hankel", h_dev, n, P, algo=args.algo)
     ev_b.record()
     torch.cuda.synchronize()
     plan_ms = ev_a.elapsed_time(ev_b)
@@ -173,21 +192,16 @@ def main():
     p99 = lat[min(len(lat) - 1, int(0.99 * len(lat)))]
     value = K / wall
 
-    C = info["Nz"] // 2 + 1
-    Nt = info["Nt"]
-    bytes_k1 = n * W * 8 + n * C * 16
-    bytes_k2 = 2 * n * C * 16 + C * Nt * 16
-    bytes_k3 = n * C * 16 + n * W * 8
-    kernels = {
-        "k_rows_fwd": (statistics.mean(k1), bytes_k1),
-        "k_cols_pass": (statistics.mean(k2), bytes_k2),
-        "k_rows_inv": (statistics.mean(k3), bytes_k3),
-    }
+    kb = kernel_bytes(args.algo, n, W, info)
+    names = KERNEL_NAMES[args.algo]
+    kernels = {names[0]: (statistics.mean(k1), kb[0]), names[1]: (statistics.mean(k2), kb[1]),
+               names[2]: (statistics.mean(k3), kb[2])}
+    bytes_k1, bytes_k2, bytes_k3 = kb
     dom = max(kernels, key=lambda k: kernels[k][0])
     dom_ms, dom_bytes = kernels[dom]
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     traffic = None
-    if dom == "k_cols_pass" and os.path.exists(TRAFFIC_FILE):
+    if dom == "k_cols_pass" and args.algo == "split_fft" and os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
         if tr.get("source_sha256") == kernel_source_hash() and tr.get("n") == n and tr.get("P") == P:
@@ -289,18 +303,65 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"lanczos-session hankel n={n} P={P}: h uniform[-1,1), "
                                f"{V} unit-norm x, plan once", "n": n, "P": P,
-                   "algo": "split_fft", "w": info["w"], "L": info["L"], "Nt": info["Nt"],
+                   "algo": args.algo, "w": info["w"], "L": info["L"], "Nt": info["Nt"],
                    "Nz": info["Nz"], "bound": info["bound"], "vectors": V,
                    "parallelism": "single-gpu"},
         "p50_ms": round(p50, 4), "p99_ms": round(p99, 4), "plan_ms": round(plan_ms, 2),
         "max_round_err": max_err,
         "roofline": roofline, "kernels": path, "graph": graph, "schoolbook_gpu": school,
         "verify": verify, "cpu_baseline": cpu,
+        "ntt_peer": None if (args.no_peer or args.algo != "split_fft")
+        else section_peer(dev, plan, h_dev, xs, ys, n, P, W, K, Wm),
         "paths_n1024": None if args.no_paths else section_paths(dev),
         "batch": None if args.no_batch else section_batch(dev),
         "serving": None if args.no_serving else section_serving(dev, procs, args),
     }
     print(json.dumps(out), flush=True)
+
+
+def section_peer(dev, fplan, h_dev, xs, ys, n, P, W, K, Wm):
+    """The exact NTT path on the same session: rate, kernels, and equality
+    with the split-FFT outputs."""
+    import torch
+
+    from paper_1402_5287_amd import hmv
+    V = xs.shape[0]
+    plan = hmv.Plan("hankel", h_dev, n, P, algo="ntt")
+    info = plan.info()
+    yn = torch.zeros_like(ys[0])
+    for k in range(Wm):
+        plan.matvec(xs[k % V], yn)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    for row in evs:
+        for e in row:
+            e.record()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        plan.matvec_events(xs[k % V], yn, evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    same = bool(torch.equal(yn, ys[(K - 1) % V]))
+    plan.matvec(xs[0], yn)
+    torch.cuda.synchronize()
+    same = same and bool(torch.equal(yn, ys[0]))
+    kb = kernel_bytes("ntt", n, W, info)
+    ks = {}
+    for j, name in enumerate(KERNEL_NAMES["ntt"]):
+        ms = statistics.mean(evs[k][j].elapsed_time(evs[k][j + 1]) for k in range(K))
+        ks[name] = {"ms": round(ms, 4), "GB/s": round(kb[j] / (ms * 1e-3) / 1e9, 1)}
+    lat = sorted(evs[k][0].elapsed_time(evs[k][3]) for k in range(K))
+    res = {"matvecs_per_s": round(K / wall, 1), "p50_ms": round(lat[len(lat) // 2], 4),
+           "p99_ms": round(lat[min(len(lat) - 1, int(0.99 * len(lat)))], 4),
+           "w": info["w"], "L": info["L"], "Nt": info["Nt"], "Nz": info["Nz"],
+           "plan_mb": round(info["plan_bytes"] / 2**20, 1), "kernels": ks,
+           "equal_to_split_fft": same}
+    log(f"ntt peer: {res}")
+    plan.close()
+    if not same:
+        raise SystemExit("NTT and split-FFT sessions disagree")
+    return res
 
 
 def _ms_between(e0, e1):

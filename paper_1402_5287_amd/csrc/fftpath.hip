@@ -221,43 +221,40 @@ __global__ void __launch_bounds__(512) k_cols_pass(const double2* __restrict__ X
   const double2* he = Hh + (int64_t)c * (2 * Nh);
   const double2* ho = he + Nh;
   double2* ycol = Y1 + tile_index(c, 0, n);
-  double2 v[16], e[16];
-  // even frequencies
+  // The column is read from HBM once: v carries the even half, o keeps the
+  // input for the odd half (its registers are live in the odd half anyway).
+  double2 v[16], o[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j)
     if (act && j < per) {
       const int s = t + Ta * j;
       v[j] = s < n ? xcol[(int64_t)(n - 1 - s) * 8] : make_double2(0.0, 0.0);
+      o[j] = v[j];
     }
+  // even frequencies
   fft_regs<LOGNH>(v, buf, -1);
 #pragma unroll
   for (int j = 0; j < 16; ++j)
     if (act && j < per) v[j] = cmul(v[j], he[t + Ta * j]);
   fft_regs<LOGNH>(v, buf, +1);
-#pragma unroll
-  for (int j = 0; j < 16; ++j) e[j] = v[j];
   // odd frequencies
 #pragma unroll
   for (int j = 0; j < 16; ++j)
-    if (act && j < per) {
-      const int s = t + Ta * j;
-      const double2 xv = s < n ? xcol[(int64_t)(n - 1 - s) * 8] : make_double2(0.0, 0.0);
-      v[j] = cmul(xv, g_rtw[s * rs]);
-    }
-  fft_regs<LOGNH>(v, buf, -1);
+    if (act && j < per) o[j] = cmul(o[j], g_rtw[(t + Ta * j) * rs]);
+  fft_regs<LOGNH>(o, buf, -1);
 #pragma unroll
   for (int j = 0; j < 16; ++j)
-    if (act && j < per) v[j] = cmul(v[j], ho[t + Ta * j]);
-  fft_regs<LOGNH>(v, buf, +1);
+    if (act && j < per) o[j] = cmul(o[j], ho[t + Ta * j]);
+  fft_regs<LOGNH>(o, buf, +1);
   // recombine and keep the window
 #pragma unroll
   for (int j = 0; j < 16; ++j)
     if (act && j < per) {
       const int s = t + Ta * j;
-      const double2 q = cmul(v[j], conj2(g_rtw[s * rs]));
+      const double2 q = cmul(o[j], conj2(g_rtw[s * rs]));
       const int ra = s - (n - 1), rb = s + Nh - (n - 1);
-      if (ra >= 0 && ra < n) ycol[(int64_t)ra * 8] = cadd(e[j], q);
-      if (rb >= 0 && rb < n) ycol[(int64_t)rb * 8] = csub(e[j], q);
+      if (ra >= 0 && ra < n) ycol[(int64_t)ra * 8] = cadd(v[j], q);
+      if (rb >= 0 && rb < n) ycol[(int64_t)rb * 8] = csub(v[j], q);
     }
 }
 
