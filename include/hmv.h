@@ -121,9 +121,11 @@ int hmv_plan_matvec(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* 
                     int64_t ws_bytes, void* stream);
 /* Same as hmv_plan_matvec, and records caller-created HIP events (hipEvent_t,
  * NULL entries skipped) on `stream` around the path's kernels, for per-kernel
- * timing: split-FFT: events[0] before the limb-axis forward pass, [1] before
- * the index-axis pass, [2] before the limb-axis inverse / carry pass, [3]
- * after it.  Other algorithms record [0] and [3] only.                       */
+ * timing.  Split-FFT and NTT: events[0] before the limb-axis forward pass,
+ * [1] before the index-axis pass, [2] before the limb-axis inverse / carry
+ * pass, [3] after it.  Karatsuba: [0] before the limb transforms of x, [1]
+ * before the leaf products (after the splitting levels), [2] before the
+ * inverse / carry pass (after the combining levels), [3] after it.          */
 int hmv_plan_matvec_events(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* ws,
                            int64_t ws_bytes, void* stream, void* const* events);
 int64_t hmv_plan_workspace_bytes(const hmv_plan* plan);

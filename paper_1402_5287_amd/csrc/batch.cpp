@@ -1,5 +1,7 @@
-// Batched launch: many independent (kind, n, P) products in one persistent
-// kernel with a device work queue (host side: sizing, descriptors, items).
+// Batched launch: many independent (kind, n, P) products, every instance's
+// work items of one pass in one launch (four launches in all), with the
+// host-side sizing, descriptors and item lists.  A single persistent launch
+// with a device work queue is kept in the source but switched off.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -269,7 +269,8 @@ def batch_workspace_bytes(problems) -> int:
 
 
 def batch_matvec(problems, ws, stream=None, check=True) -> int:
-    """All products of `problems` (from batch_problems) in one persistent launch."""
+    """All products of `problems` (from batch_problems): one launch per pass,
+    each launch covering every instance (four launches)."""
     rc = lib().hmv_batch_matvec(ctypes.cast(problems, ctypes.c_void_p), len(problems), _ptr(ws),
                                 ws.numel(), _stream(stream))
     if check:
