@@ -28,6 +28,44 @@ __device__ inline void status_or(DevStatus* st, uint32_t f) {
   if (st) atomicOr(&st->flags, f);
 }
 
+// Record the work-group's largest rounding distance m (each thread passes its
+// own, m >= 0).  One atomic per work-group at most, and none when the value
+// already recorded is at least as large: thousands of work-groups updating
+// one word would otherwise serialise on it.  Non-negative doubles order like
+// their bit patterns.  `slots` = 16 LDS doubles; ends with a barrier.
+__device__ inline void status_max_err(DevStatus* st, double m, double* slots) {
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) slots[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0 && st) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, slots[k]);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+    unsigned long long* dst = reinterpret_cast<unsigned long long*>(&st->max_err_bits);
+    if (bits > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(dst, bits);
+  }
+}
+
+// Copy W words from global memory into LDS.  Each thread issues its loads
+// four at a time (clamped, always in bounds) before storing any of them, so
+// they are in flight together.  The caller synchronises afterwards.
+__device__ inline void load_words(const uint64_t* __restrict__ src, int W, uint64_t* dst) {
+  const int T = blockDim.x, t = threadIdx.x;
+  for (int q0 = t; q0 < W; q0 += 4 * T) {
+    uint64_t r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u * T;
+      r[u] = src[q < W ? q : W - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u * T;
+      if (q < W) dst[q] = r[u];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // block-wide exclusive scan of an associative operator on small codes.
 // op(a, b) means "a first, then b".  blockDim.x must be a multiple of 64.

@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   const int T = blockDim.x, t = threadIdx.x;
   const int M = 1 << logM;
   const int src = gather_row(r, gather_n);
-  for (int q = t; q < W; q += T) wd[q] = in[(int64_t)src * W + q];
+  load_words(in + (int64_t)src * W, W, wd);
   __syncthreads();
   if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
   // digit e is the real (e even) or imaginary (e odd) part of element e/2
@@ -182,23 +182,26 @@ __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H
   double2* ho = he + Nh;
   double2 v[16];
   for (int half = 0; half < 2; ++half) {
+    // one guarded block per loop (not one per element), with clamped
+    // in-bounds addresses, so that all loads are in flight together
+    if (act) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      if (act && j < per) {
+      for (int j = 0; j < per; ++j) {
         const int s = t + Ta * j;
-        const double2 lo = s < rows ? col[(int64_t)s * 8] : make_double2(0.0, 0.0);
-        const double2 hi = s + Nh < rows ? col[(int64_t)(s + Nh) * 8] : make_double2(0.0, 0.0);
-        v[j] = half == 0 ? cadd(lo, hi) : cmul(csub(lo, hi), g_rtw[s * rs]);
+        const double2 lo = col[(int64_t)(s < rows ? s : 0) * 8];
+        const double2 hi = col[(int64_t)(s + Nh < rows ? s + Nh : 0) * 8];
+        const double2 l = s < rows ? lo : make_double2(0.0, 0.0);
+        const double2 u = s + Nh < rows ? hi : make_double2(0.0, 0.0);
+        v[j] = half == 0 ? cadd(l, u) : cmul(csub(l, u), g_rtw[s * rs]);
       }
     }
     fft_regs<LOGNH>(v, buf, -1);
     double2* dst = half == 0 ? he : ho;
+    if (act) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (act && j < per) {
-        const int f = t + Ta * j;
-        dst[f] = make_double2(v[j].x * scale, v[j].y * scale);
-      }
+      for (int j = 0; j < per; ++j)
+        dst[t + Ta * j] = make_double2(v[j].x * scale, v[j].y * scale);
+    }
   }
 }
 
@@ -223,39 +226,48 @@ __global__ void __launch_bounds__(512) k_cols_pass(const double2* __restrict__ X
   double2* ycol = Y1 + tile_index(c, 0, n);
   // The column is read from HBM once: v carries the even half, o keeps the
   // input for the odd half (its registers are live in the odd half anyway).
+  // Every per-element loop sits in one guarded block with in-bounds
+  // (clamped) addresses, so its loads are issued together rather than one
+  // round trip per element.
   double2 v[16], o[16];
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) {
+    for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
-      v[j] = s < n ? xcol[(int64_t)(n - 1 - s) * 8] : make_double2(0.0, 0.0);
+      const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * 8];
+      v[j] = s < n ? xv : make_double2(0.0, 0.0);
       o[j] = v[j];
     }
+  }
   // even frequencies
   fft_regs<LOGNH>(v, buf, -1);
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) v[j] = cmul(v[j], he[t + Ta * j]);
+    for (int j = 0; j < per; ++j) v[j] = cmul(v[j], he[t + Ta * j]);
+  }
   fft_regs<LOGNH>(v, buf, +1);
   // odd frequencies
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) o[j] = cmul(o[j], g_rtw[(t + Ta * j) * rs]);
+    for (int j = 0; j < per; ++j) o[j] = cmul(o[j], g_rtw[(t + Ta * j) * rs]);
+  }
   fft_regs<LOGNH>(o, buf, -1);
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) o[j] = cmul(o[j], ho[t + Ta * j]);
+    for (int j = 0; j < per; ++j) o[j] = cmul(o[j], ho[t + Ta * j]);
+  }
   fft_regs<LOGNH>(o, buf, +1);
   // recombine and keep the window
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) {
+    for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
       const double2 q = cmul(o[j], conj2(g_rtw[s * rs]));
       const int ra = s - (n - 1), rb = s + Nh - (n - 1);
       if (ra >= 0 && ra < n) ycol[(int64_t)ra * 8] = cadd(v[j], q);
       if (rb >= 0 && rb < n) ycol[(int64_t)rb * 8] = csub(v[j], q);
     }
+  }
 }
 
 // Row pass, inverse: real inverse FFT over the limb axis, round every
@@ -270,34 +282,43 @@ __global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__
                                                      DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint32_t red[32];
+  __shared__ double errs[16];
   __shared__ double2 ytop;                 // Y[M]
   const int i = blockIdx.x;
   if (i >= n) return;
   constexpr int M = 1 << LOGM;
   constexpr int Ta = M >= 16 ? M >> 4 : 1, per = M >= 16 ? 16 : M;
   constexpr int rs = kRealTwN / (2 * M);
-  const int T = blockDim.x, t = threadIdx.x;
+  const int t = threadIdx.x;
   const bool act = t < Ta;
-  // packing roots first: independent of the data
-  double2 wk[16];
+  // the row and the packing roots, all loads in flight together (one
+  // guarded block; element k = t + Ta j covers every k < M)
+  double2 wk[16], v[16];
+  const double2 top = Y1[tile_index(M, i, n)];
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) wk[j] = conj2(g_rtw[(t + Ta * j) * rs]);
-  for (int k = t; k < M; k += T) buf[swz(k)] = Y1[tile_index(k, i, n)];
-  if (t == 0) ytop = Y1[tile_index(M, i, n)];
+    for (int j = 0; j < per; ++j) {
+      const int k = t + Ta * j;
+      v[j] = Y1[tile_index(k, i, n)];
+      wk[j] = conj2(g_rtw[k * rs]);
+    }
+#pragma unroll
+    for (int j = 0; j < per; ++j) buf[swz(t + Ta * j)] = v[j];
+  }
+  if (t == 0) ytop = top;
   __syncthreads();
   // Z[k] = (Y[k] + conj Y[M-k]) + i w^-k (Y[k] - conj Y[M-k]),  k < M
-  double2 v[16];
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) {
+    for (int j = 0; j < per; ++j) {
       const int k = t + Ta * j;
-      const double2 yk = buf[swz(k)];
+      const double2 yk = v[j];
       const double2 ym = k == 0 ? ytop : buf[swz(M - k)];
       const double2 E = cadd(yk, conj2(ym)), D = csub(yk, conj2(ym));
       const double2 Q = cmul(D, wk[j]);
       v[j] = make_double2(E.x - Q.y, E.y + Q.x);
     }
+  }
   __syncthreads();
   fft_regs<LOGM>(v, buf, +1);
   // element m = t + Ta j holds coefficients 2m (real part) and 2m+1 (imaginary)
@@ -305,9 +326,9 @@ __global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__
   const int NC = 2 * L - 1;
   double maxerr = 0.0;
   int bad = 0;
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) {
+    for (int j = 0; j < per; ++j) {
       const int m = t + Ta * j;
       const double s0 = rint(v[j].x), s1 = rint(v[j].y);
       maxerr = fmax(maxerr, fmax(fabs(v[j].x - s0), fabs(v[j].y - s1)));
@@ -317,10 +338,8 @@ __global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__
       if (2 * m + 1 < NC) coef[2 * m + 1] = i1;
       else if (i1 != 0) bad = 1;
     }
-  for (int o = 32; o > 0; o >>= 1) maxerr = fmax(maxerr, __shfl_xor(maxerr, o, 64));
-  if ((t & 63) == 0 && st)
-    atomicMax(reinterpret_cast<unsigned long long*>(&st->max_err_bits),
-              (unsigned long long)__double_as_longlong(maxerr));
+  }
+  status_max_err(st, maxerr, errs);
   bad = __syncthreads_or(bad);
   if (bad && t == 0) status_or(st, ST_BOUND);
   uint64_t* sw = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(buf) + carry_off);
@@ -534,7 +553,7 @@ __device__ void b_row_fwd(const uint64_t* in, int W, int P, int w, int L, int ga
   const int T = blockDim.x, t = threadIdx.x;
   const int M = 1 << logM;
   const int src = gather_row(r, gather_n);
-  for (int q = t; q < W; q += T) wd[q] = in[(int64_t)src * W + q];
+  load_words(in + (int64_t)src * W, W, wd);
   __syncthreads();
   if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
   double* bd = reinterpret_cast<double*>(buf);
@@ -618,6 +637,7 @@ __device__ void b_col_pass(const double2* X1, const double2* Hh, int n, int logN
 __device__ void b_row_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
                           int out_reverse, uint64_t* y, int i, double2* buf, uint32_t* red,
                           DevStatus* st) {
+  __shared__ double errs[16];
   const int T = blockDim.x, t = threadIdx.x;
   const int M = 1 << logM;
   const int rs = kRealTwN / (2 * M);
@@ -669,10 +689,7 @@ __device__ void b_row_inv(const double2* Y1, int n, int logM, int L, int w, int 
       else if (i1 != 0) bad = 1;
     }
   }
-  for (int o = 32; o > 0; o >>= 1) maxerr = fmax(maxerr, __shfl_xor(maxerr, o, 64));
-  if ((t & 63) == 0 && st)
-    atomicMax(reinterpret_cast<unsigned long long*>(&st->max_err_bits),
-              (unsigned long long)__double_as_longlong(maxerr));
+  status_max_err(st, maxerr, errs);
   bad = __syncthreads_or(bad);
   if (bad && t == 0) status_or(st, ST_BOUND);
   const int carry_off = (NC * 8 + 15) / 16 * 16;

@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(512) k_ntt_rows_fwd(const uint64_t* __restrict
   const int T = blockDim.x, t = threadIdx.x, N = 1 << logN;
   if (t < 16) r16[t] = g_nr16[t];
   const int src = n_gather_row(r, gather_n);
-  for (int q = t; q < W; q += T) wd[q] = in[(int64_t)src * W + q];
+  load_words(in + (int64_t)src * W, W, wd);
   __syncthreads();
   if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
   for (int e = L + t; e < N; e += T) nbuf[nswz(e)] = 0;
@@ -105,7 +105,20 @@ __global__ void __launch_bounds__(512) k_ntt_rows_inv(const uint64_t* __restrict
   if (i >= n) return;
   const int T = blockDim.x, t = threadIdx.x, N = 1 << logN;
   if (t < 16) r16[t] = g_nr16[16 + t];
-  for (int k = t; k < N; k += T) nbuf[nswz(k)] = Y[ntile(k, i, n, logT)];
+  {
+    // element k = t + T a; the loads of a thread are issued together
+    uint64_t ld[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int k = t + a * T;
+      ld[a] = Y[ntile(k < N ? k : 0, i, n, logT)];
+    }
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int k = t + a * T;
+      if (k < N) nbuf[nswz(k)] = ld[a];
+    }
+  }
   __syncthreads();
   ntt_lds(nbuf, logN, 1, r16);
   const int NC = 2 * L - 1;
@@ -159,19 +172,23 @@ __global__ void __launch_bounds__(512) k_ntt_cols_plan(const uint64_t* __restric
   uint64_t* he = Hh + (int64_t)c * (2 * Nh);
   uint64_t v[16];
   for (int half = 0; half < 2; ++half) {
+    // one guarded block per loop with clamped addresses: loads in flight together
+    if (act) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (act && j < per) {
+      for (int j = 0; j < per; ++j) {
         const int s = t + Ta * j;
-        const uint64_t lo = s < rows ? H1[ntile(c, s, rows, 4)] : 0;
-        const uint64_t hi = s + Nh < rows ? H1[ntile(c, s + Nh, rows, 4)] : 0;
+        const uint64_t l = H1[ntile(c, s < rows ? s : 0, rows, 4)];
+        const uint64_t u = H1[ntile(c, s + Nh < rows ? s + Nh : 0, rows, 4)];
+        const uint64_t lo = s < rows ? l : 0, hi = s + Nh < rows ? u : 0;
         v[j] = half == 0 ? gl_add(lo, hi) : gl_mul(gl_sub(lo, hi), g_nsplit[s * ss]);
       }
+    }
     ntt_regs<LOGNH>(v, nbuf, 0, r16);
     uint64_t* dst = he + half * Nh;
+    if (act) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (act && j < per) dst[t + Ta * j] = gl_mul(v[j], scale);
+      for (int j = 0; j < per; ++j) dst[t + Ta * j] = gl_mul(v[j], scale);
+    }
   }
 }
 
@@ -194,42 +211,46 @@ __global__ void __launch_bounds__(512) k_ntt_cols_pass(const uint64_t* __restric
   }
   const uint64_t* he = Hh + (int64_t)c * (2 * Nh);
   const uint64_t* ho = he + Nh;
-  uint64_t v[16], e[16];
+  // The column is read once (o keeps it for the odd half); every
+  // per-element loop is one guarded block with clamped addresses, so its
+  // loads are in flight together.
+  uint64_t v[16], o[16];
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) {
+    for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
-      v[j] = s < n ? X1[ntile(c, n - 1 - s, n, 4)] : 0;
+      const uint64_t xv = X1[ntile(c, s < n ? n - 1 - s : 0, n, 4)];
+      v[j] = s < n ? xv : 0;
+      o[j] = v[j];
     }
+  }
   __syncthreads();
   ntt_regs<LOGNH>(v, nbuf, 0, r16f);
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) v[j] = gl_mul(v[j], he[t + Ta * j]);
+    for (int j = 0; j < per; ++j) v[j] = gl_mul(v[j], he[t + Ta * j]);
+  }
   ntt_regs<LOGNH>(v, nbuf, 1, r16i);
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j) e[j] = v[j];
+    for (int j = 0; j < per; ++j) o[j] = gl_mul(o[j], g_nsplit[(t + Ta * j) * ss]);
+  }
+  ntt_regs<LOGNH>(o, nbuf, 0, r16f);
+  if (act) {
 #pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) {
+    for (int j = 0; j < per; ++j) o[j] = gl_mul(o[j], ho[t + Ta * j]);
+  }
+  ntt_regs<LOGNH>(o, nbuf, 1, r16i);
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
-      const uint64_t xv = s < n ? X1[ntile(c, n - 1 - s, n, 4)] : 0;
-      v[j] = gl_mul(xv, g_nsplit[s * ss]);
-    }
-  ntt_regs<LOGNH>(v, nbuf, 0, r16f);
-#pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) v[j] = gl_mul(v[j], ho[t + Ta * j]);
-  ntt_regs<LOGNH>(v, nbuf, 1, r16i);
-#pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (act && j < per) {
-      const int s = t + Ta * j;
-      const uint64_t q = gl_mul(v[j], g_nsplit[kNttSplitEntries + s * ss]);
+      const uint64_t q = gl_mul(o[j], g_nsplit[kNttSplitEntries + s * ss]);
       const int ra = s - (n - 1), rb = s + Nh - (n - 1);
-      if (ra >= 0 && ra < n) Y1[ntile(c, ra, n, 4)] = gl_add(e[j], q);
-      if (rb >= 0 && rb < n) Y1[ntile(c, rb, n, 4)] = gl_sub(e[j], q);
+      if (ra >= 0 && ra < n) Y1[ntile(c, ra, n, 4)] = gl_add(v[j], q);
+      if (rb >= 0 && rb < n) Y1[ntile(c, rb, n, 4)] = gl_sub(v[j], q);
     }
+  }
 }
 
 // ------------------------------------------------------------------ Karatsuba
