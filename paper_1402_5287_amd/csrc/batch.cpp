@@ -43,9 +43,8 @@ bool batch_inst_sizes(int64_t n, int32_t P, FftSizes* out) {
     const double b = fft_conv_bound(nh, nx, k, fft_twiddle_beta());
     const double cmax = (double)n * z.L * std::ldexp(1.0, 2 * (w - 1));
     const int NC = 2 * z.L - 1;
-    const int W = (int)words_of(P);
-    const size_t carry_end = (size_t)(NC * 8 + 15) / 16 * 16 + (size_t)carry_lds_bytes(NC, w, P, W);
-    if (b < 0.5 && cmax < std::ldexp(1.0, 52) && carry_end <= kBatchDynLds) {
+    const size_t carry_end = (size_t)(NC * 8 + 15) / 16 * 16 + (size_t)carry_lds_bytes(kBatchThreads);
+    if (b < 0.5 && cmax < std::ldexp(1.0, 50) && carry_end <= kBatchDynLds) {
       *out = z;
       return true;
     }

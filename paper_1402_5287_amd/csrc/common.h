@@ -28,22 +28,50 @@ __device__ inline void status_or(DevStatus* st, uint32_t f) {
   if (st) atomicOr(&st->flags, f);
 }
 
-// Record the work-group's largest rounding distance m (each thread passes its
-// own, m >= 0).  One atomic per work-group at most, and none when the value
-// already recorded is at least as large: thousands of work-groups updating
-// one word would otherwise serialise on it.  Non-negative doubles order like
-// their bit patterns.  `slots` = 16 LDS doubles; ends with a barrier.
-__device__ inline void status_max_err(DevStatus* st, double m, double* slots) {
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) slots[threadIdx.x >> 6] = m;
+// Per-row status of the rounding step: every thread folds its largest
+// rounding distance and its bound flag into two LDS slots (LDS atomics, no
+// shuffles); after one barrier thread 0 publishes them with at most one
+// global atomic each, the max-error one only when it raises the recorded
+// value (thousands of work-groups updating one word would otherwise
+// serialise on it).  Non-negative doubles order like their bit patterns.
+struct RowStatus {
+  unsigned long long err;
+  uint32_t bad;
+};
+// thread 0, before the work-group's first barrier
+__device__ inline void row_status_init(RowStatus* rs) {
+  if (threadIdx.x == 0) {
+    rs->err = 0ull;
+    rs->bad = 0u;
+  }
+}
+__device__ inline void row_status_add(RowStatus* rs, double err, int bad) {
+  atomicMax(&rs->err, (unsigned long long)__double_as_longlong(err));
+  if (bad) atomicOr(&rs->bad, 1u);
+}
+// ends with a barrier
+__device__ inline void row_status_publish(RowStatus* rs, DevStatus* st) {
   __syncthreads();
   if (threadIdx.x == 0 && st) {
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = fmax(m, slots[k]);
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(m);
+    const unsigned long long bits = rs->err;
     unsigned long long* dst = reinterpret_cast<unsigned long long*>(&st->max_err_bits);
     if (bits > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       atomicMax(dst, bits);
+    if (rs->bad) status_or(st, ST_BOUND);
   }
+}
+
+// Every exact coefficient of the binary64 path is below this in magnitude
+// (the planner's constraint n L 4^(w-1) < 2^50), so round_to_int applies.
+constexpr double kCoefLimit = 1125899906842624.0;   // 2^50
+
+// Nearest integer of v (ties to even) for |v| < 2^51, as a double and as an
+// int64: adding 1.5 * 2^52 leaves the rounded value in the low mantissa bits.
+__device__ inline int64_t round_to_int(double v, double* rounded) {
+  const double kMagic = 6755399441055744.0;        // 1.5 * 2^52
+  const double t = v + kMagic;
+  *rounded = t - kMagic;
+  return (int64_t)(__double_as_longlong(t) - __double_as_longlong(kMagic));
 }
 
 // Copy W words from global memory into LDS.  Each thread issues its loads
@@ -69,34 +97,27 @@ __device__ inline void load_words(const uint64_t* __restrict__ src, int W, uint6
 // ---------------------------------------------------------------------------
 // block-wide exclusive scan of an associative operator on small codes.
 // op(a, b) means "a first, then b".  blockDim.x must be a multiple of 64.
-// `lds` needs 32 uint32 slots.
+// `lds` needs 32 uint32 slots; the caller synchronises before writing them
+// again.
 // ---------------------------------------------------------------------------
 template <class Op>
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t ident, Op op, uint32_t* lds) {
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   uint32_t inc = v;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
     uint32_t o = __shfl_up(inc, d, 64);
     if (lane >= d) inc = op(o, inc);
   }
-  __syncthreads();
+  __syncthreads();                 // earlier readers of lds are done
   if (lane == 63) lds[wv] = inc;
   __syncthreads();
-  if (t == 0) {
-    uint32_t acc = ident;
-    for (int k = 0; k < nw; ++k) {
-      uint32_t tot = lds[k];
-      lds[k] = acc;              // exclusive prefix of wave k
-      acc = op(acc, tot);
-    }
-  }
-  __syncthreads();
+  // every wave composes the totals of the waves before it (at most 15)
+  uint32_t acc = ident;
+  for (int k = 0; k < wv; ++k) acc = op(acc, lds[k]);
   uint32_t prev = __shfl_up(inc, 1, 64);
   if (lane == 0) prev = ident;
-  uint32_t res = op(lds[wv], prev);
-  __syncthreads();
-  return res;
+  return op(acc, prev);
 }
 
 // carry function of the balancing pass: 0 = kill (out 0), 1 = generate
@@ -184,111 +205,180 @@ __device__ inline void split_balanced(const uint64_t* wd, int W, int w, int L, S
 // ---------------------------------------------------------------------------
 // Exact carry, round and pack
 // ---------------------------------------------------------------------------
-constexpr int kCarryMaxPer = 16;
-
-// LDS words needed by carry_round_pack: NWS words for S plus NWS small carries.
-__host__ __device__ inline int carry_words(int NC, int w, int P, int W) {
-  const int a = (int)(((int64_t)w * (NC - 1)) / 64) + 3;
-  const int b = (P >> 6) + W + 2;
-  return a > b ? a : b;
-}
-__host__ __device__ inline int carry_lds_bytes(int NC, int w, int P, int W) {
-  return carry_words(NC, w, P, W) * 12;
-}
-
-__device__ inline __int128 word_column(const int64_t* coef, int NC, int w, int q) {
-  // A_q = sum_{e: floor(we/64)=q} lo(coef_e 2^r) + sum_{e: floor(we/64)=q-1} hi(coef_e 2^r)
-  __int128 acc = 0;
-  int elo = (64 * q + w - 1) / w, ehi = min(NC, (64 * (q + 1) + w - 1) / w);
-  for (int e = elo; e < ehi; ++e) {
-    const int r = w * e - 64 * q;
-    const unsigned __int128 V = (unsigned __int128)(__int128)coef[e] << r;
-    acc += (__int128)(uint64_t)V;
-  }
-  if (q >= 1) {
-    elo = (64 * (q - 1) + w - 1) / w;
-    ehi = min(NC, (64 * q + w - 1) / w);
-    for (int e = elo; e < ehi; ++e) {
-      const int r = w * e - 64 * (q - 1);
-      const __int128 V = (__int128)((unsigned __int128)(__int128)coef[e] << r);
-      acc += (__int128)(V >> 64);
-    }
-  }
-  return acc;
-}
+// LDS scratch of carry_round_pack for a work-group of T threads.
+__host__ __device__ inline int carry_lds_bytes(int T) { return 8 * T + 64; }
 
 // Exact carry, round and pack.
-// S = sum_{e < NC} coef[e] * 2^(w e) with int64 coefficients (LDS).
-// Y = round-half-even(S / 2^P) is written as W two's complement words to y.
-// sw: LDS scratch of carry_lds_bytes() bytes; red: 32 uint32 LDS slots.
-// S is cut into 64-bit columns A_q = v_q + c_q 2^64 (v_q unsigned, c_q a
-// small signed carry); word q then holds v_q + c_{q-1} + kappa_q where the
-// ripple carry kappa in {-1, 0, 1} is resolved by a block scan of the maps
-// kappa_q -> kappa_{q+1}.
-__device__ inline void carry_round_pack(const int64_t* coef, int NC, int w, int P, int W,
-                                        uint64_t* sw, int NWS, uint64_t* __restrict__ y,
-                                        uint32_t* red) {
+// S = sum_{e < NC} coef[e] 2^(w e) with int64 coefficients in LDS, |coef| <
+// 2^62.  Y = round-half-even(S / 2^P) is written as W two's complement
+// words to y.  coef is overwritten with the limbs of S; cs: LDS scratch of
+// carry_lds_bytes(blockDim.x) bytes; red: 32 uint32 LDS slots.
+//
+// Thread t owns a chunk of E consecutive coefficients (E odd, so that the
+// strided LDS accesses spread over the banks, and E w >= 60).
+//  1. Each chunk is normalised on its own: limbs in [0, 2^w) (floor
+//     division), leaving a carry C_t with |C_t| < 2^55 for the next chunk.
+//  2. Adding C_{t-1} to chunk t may carry one more unit out of it, in
+//     either direction; what leaves chunk t for an extra incoming
+//     kappa in {-1, 0, 1} depends only on its low limbs (which absorb
+//     C_{t-1}) and on whether its other limbs are all 0 or all 2^w - 1.
+//     These maps are composed by a block scan, which gives every chunk its
+//     kappa.
+//  3. Each chunk adds C_{t-1} + kappa; the top chunk keeps what leaves the
+//     limbs plus its own C (S = sum limbs 2^(w e) + top 2^(w NC)).
+// Then the round bit (P-1), the sticky OR below it and bit P decide the
+// round-half-even increment of floor(S / 2^P), whose words are cut from the
+// limbs; the increment ripples through the lowest all-ones words.
+// Limbs a thread keeps in registers during the carry passes; a longer chunk
+// (only for very large P at small widths) runs the same passes from LDS.
+constexpr int kCarryRegs = 32;
+
+__device__ inline void carry_round_pack(int64_t* coef, int NC, int w, int P, int W, int64_t* cs,
+                                        uint64_t* __restrict__ y, uint32_t* red) {
   const int T = blockDim.x, t = threadIdx.x;
-  const int per = (NWS + T - 1) / T;
-  const int q0 = min(NWS, t * per), q1 = min(NWS, q0 + per);
-  int32_t* cv = reinterpret_cast<int32_t*>(sw + NWS);     // c_{q-1} per word q
-  int64_t cprev = 0;
-  if (q0 >= 1 && q0 < q1) cprev = (int64_t)(word_column(coef, NC, w, q0 - 1) >> 64);
-  WordOp op;
-  uint32_t f = kWordIdent;
-  for (int q = q0; q < q1; ++q) {
-    const __int128 A = word_column(coef, NC, w, q);
-    const uint64_t v = (uint64_t)A;
-    sw[q] = v;
-    cv[q] = (int32_t)cprev;
-    uint32_t g = 0;
+  const int64_t mask = (int64_t(1) << w) - 1;
+  const int kmin = (60 + w - 1) / w;
+  int E = (NC + T - 1) / T;
+  if (E < kmin) E = kmin;
+  E |= 1;
+  const int nch = (NC + E - 1) / E;
+  const int e0 = t * E, e1 = min(NC, e0 + E);
+  const bool own = t < nch;
+  const int len = own ? e1 - e0 : 0;
+  const bool in_regs = E <= kCarryRegs;         // uniform
+  int64_t r[kCarryRegs];
+  // 1. chunk-local normalisation
+  int64_t cown = 0;
+  if (in_regs) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const __int128 s = (__int128)v + cprev + (i - 1);
-      const int kap = (int)(s >> 64);           // -1, 0 or 1
-      g |= (uint32_t)(kap + 1) << (2 * i);
+    for (int j = 0; j < kCarryRegs; ++j) {
+      const int e = e0 + j < NC ? e0 + j : NC - 1;
+      r[j] = coef[e];
     }
-    f = op(f, g);
-    cprev = (int64_t)(A >> 64);
+#pragma unroll
+    for (int j = 0; j < kCarryRegs; ++j) {
+      const int64_t c = r[j] + cown;
+      const bool in = j < len;
+      r[j] = in ? (c & mask) : 0;
+      cown = in ? (c >> w) : cown;
+    }
+  } else if (own) {
+    for (int e = e0; e < e1; ++e) {
+      const int64_t c = coef[e] + cown;
+      coef[e] = c & mask;
+      cown = c >> w;
+    }
   }
-  const uint32_t fin = block_exclusive_scan(f, kWordIdent, op, red);
-  int kappa = (int)(fin >> 2 & 3u) - 1;        // applied to kappa_0 = 0 (index 1)
-  for (int q = q0; q < q1; ++q) {
-    const __int128 s = (__int128)sw[q] + cv[q] + kappa;
-    sw[q] = (uint64_t)s;
-    kappa = (int)(s >> 64);
-  }
+  if (own) cs[t] = cown;
   __syncthreads();
-  // round half to even at bit P
-  const int pb = P - 1;
-  const int bitP1 = (int)((sw[pb >> 6] >> (pb & 63)) & 1ull);
-  const int qlsb = (int)((sw[P >> 6] >> (P & 63)) & 1ull);
+  const int64_t cin = (own && t > 0) ? cs[t - 1] : 0;
+  // 2. carry map of the chunk: what leaves it when cin + kappa enters, for
+  //    kappa = -1, 0, 1 (three independent floor-division chains; each
+  //    result is -1, 0 or 1 because |cin| + 1 < 2^(w E)).  Identity for the
+  //    top chunk and idle threads.
+  uint32_t g = kWordIdent;
+  if (own && t < nch - 1) {
+    int64_t cm = cin - 1, c0 = cin, cp = cin + 1;
+    if (in_regs) {
+#pragma unroll
+      for (int j = 0; j < kCarryRegs; ++j) {
+        const bool in = j < len;
+        cm = in ? (r[j] + cm) >> w : cm;
+        c0 = in ? (r[j] + c0) >> w : c0;
+        cp = in ? (r[j] + cp) >> w : cp;
+      }
+    } else {
+      for (int e = e0; e < e1; ++e) {
+        cm = (coef[e] + cm) >> w;
+        c0 = (coef[e] + c0) >> w;
+        cp = (coef[e] + cp) >> w;
+      }
+    }
+    g = (uint32_t)(cm + 1) | ((uint32_t)(c0 + 1) << 2) | ((uint32_t)(cp + 1) << 4);
+  }
+  const uint32_t pre = block_exclusive_scan(g, kWordIdent, WordOp(), red);
+  const int kap = (int)((pre >> 2) & 3u) - 1;      // the map applied to kappa_0 = 0
+  // 3. incoming carry; sticky bit (any 1 below bit P-1) from the final limbs
+  const int ep = (P - 1) / w, rp = (P - 1) - ep * w;
+  const int64_t rpmask = (int64_t(1) << rp) - 1;
+  int64_t carry = cin + kap;
   int st = 0;
-  for (int q = t; q <= (pb >> 6); q += T) {
-    uint64_t word = sw[q];
-    if (q == (pb >> 6)) word &= (pb & 63) ? ((1ull << (pb & 63)) - 1ull) : 0ull;
-    if (word) st = 1;
-  }
-  const int sticky = __syncthreads_or(st);
-  const int up = bitP1 && (sticky || qlsb);
-  // words of floor(S / 2^P); the increment ripples through low all-ones words
-  if (t == 0) red[0] = (uint32_t)W;
-  __syncthreads();
-  const int sh = P & 63, base = P >> 6;
-  for (int m = t; m < W; m += T) {
-    const uint64_t lo = sw[base + m] >> sh;
-    const uint64_t hi = sh ? (sw[base + m + 1] << (64 - sh)) : 0ull;
-    if ((lo | hi) != ~0ull) atomicMin(&red[0], (uint32_t)m);
-  }
-  __syncthreads();
-  const int first = (int)red[0];
-  for (int m = t; m < W; m += T) {
-    uint64_t ym = (sw[base + m] >> sh) | (sh ? (sw[base + m + 1] << (64 - sh)) : 0ull);
-    if (up) {
-      if (m < first) ym = 0ull;
-      else if (m == first) ym += 1ull;
+  if (in_regs) {
+#pragma unroll
+    for (int j = 0; j < kCarryRegs; ++j) {
+      const int64_t c = r[j] + carry;
+      const bool in = j < len;
+      r[j] = c & mask;
+      carry = in ? (c >> w) : carry;
+      const int e = e0 + j;
+      const int64_t low = e < ep ? r[j] : (e == ep ? (r[j] & rpmask) : 0);
+      if (in && low) st = 1;
     }
-    y[m] = ym;
+    if (own) {
+#pragma unroll
+      for (int j = 0; j < kCarryRegs; ++j)
+        if (j < len) coef[e0 + j] = r[j];
+    }
+  } else if (own) {
+    for (int e = e0; e < e1; ++e) {
+      const int64_t c = coef[e] + carry;
+      coef[e] = c & mask;
+      carry = c >> w;
+      const int64_t low = e < ep ? coef[e] : (e == ep ? (coef[e] & rpmask) : 0);
+      if (low) st = 1;
+    }
+  }
+  if (own && t == nch - 1) cs[T] = carry + cown;   // the top chunk's own C too
+  if (t == 0) red[31] = (uint32_t)W;               // first word that is not all ones
+  const int sticky = __syncthreads_or(st);
+  const int64_t top = cs[T];
+  const int64_t ncw = (int64_t)NC * w;             // > P: every bit below P+1 is in a limb
+  const int rbit = (int)((coef[ep] >> rp) & 1);
+  const int el = P / w;
+  const int lsb = (int)((coef[el] >> (P - el * w)) & 1);
+  const int up = rbit && (sticky || lsb);
+  // words of floor(S / 2^P): bits [P + 64 m, P + 64 m + 64) of S; for
+  // w >= 8 at most 64 / w + 2 <= 10 limbs overlap a word
+  auto word_at = [&](int b) -> uint64_t {
+    if (b >= ncw) return (uint64_t)(top >> (b - ncw < 63 ? b - ncw : 63));
+    const int e = b / w;
+    const int off = b - e * w;
+    if (w < 8) {                                    // more limbs per word than the window
+      unsigned __int128 acc = (unsigned __int128)((uint64_t)coef[e] >> off);
+      int nb = w - off, k = e + 1;
+      for (; nb < 64 && k < NC; ++k, nb += w) acc |= (unsigned __int128)(uint64_t)coef[k] << nb;
+      if (nb < 64) acc |= (unsigned __int128)(uint64_t)top << nb;
+      return (uint64_t)acc;
+    }
+    int64_t l[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) l[j] = coef[e + j < NC ? e + j : NC - 1];
+    unsigned __int128 acc = (unsigned __int128)((uint64_t)l[0] >> off);
+    int nb = w - off;
+#pragma unroll
+    for (int j = 1; j < 10; ++j) {
+      if (nb < 64) {
+        const uint64_t v = e + j < NC ? (uint64_t)l[j] : (uint64_t)top;
+        acc |= (unsigned __int128)v << nb;
+        nb = e + j < NC ? nb + w : 64;
+      }
+    }
+    return (uint64_t)acc;
+  };
+  // floor words go straight out; with a round-up increment the words below
+  // the first one that is not all ones become 0 and that one gains 1
+  int firstme = W;
+  for (int m = t; m < W; m += T) {
+    const uint64_t um = word_at(P + 64 * m);
+    y[m] = um;
+    if (um != ~0ull && m < firstme) firstme = m;
+  }
+  if (up && firstme < W) atomicMin(&red[31], (uint32_t)firstme);
+  __syncthreads();
+  if (up) {
+    const int first = (int)red[31];
+    for (int m = t; m <= first && m < W; m += T)
+      y[m] = m < first ? 0ull : word_at(P + 64 * m) + 1ull;
   }
   __syncthreads();
 }

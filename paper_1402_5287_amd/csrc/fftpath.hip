@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(256) k_h_norms(const uint64_t* __restrict__ h,
   const int r = blockIdx.x;
   if (r >= rows) return;
   const int src = gather_row(r, gather_n);
-  for (int q = threadIdx.x; q < W; q += blockDim.x) wd[q] = h[(int64_t)src * W + q];
+  load_words(h + (int64_t)src * W, W, wd);
   __syncthreads();
   if (!number_in_range(wd, W, P) && threadIdx.x == 0) status_or(st, ST_RANGE);
   for (int w = wlo; w <= whi; ++w) {
@@ -115,6 +115,35 @@ __global__ void __launch_bounds__(256) k_h_norms(const uint64_t* __restrict__ h,
       atomicAdd(&norms[w - wlo], s);
     }
     __syncthreads();
+  }
+}
+
+// Real-input packing of the M-point transform Z held in buf (the limb
+// sequence as M complex points) into the M + 1 bins of the real transform,
+//   X[k] = 1/2 (Z[k] + conj Z[M-k]) - i/2 w^k (Z[k] - conj Z[M-k]),
+// stored to row r of the tiled spectrum.  A thread's root loads are issued
+// eight at a time so that they are in flight together.
+__device__ inline void pack_real_row(const double2* buf, int M, double2* __restrict__ out, int r,
+                                     int rows_alloc) {
+  const int T = blockDim.x, t = threadIdx.x;
+  const int rs = kRealTwN / (2 * M);
+  for (int k0 = t; k0 <= M; k0 += 8 * T) {
+    double2 wv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u * T;
+      wv[u] = g_rtw[(k <= M ? k : M) * rs];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u * T;
+      if (k <= M) {
+        const double2 zk = buf[swz(k & (M - 1))], zm = buf[swz((M - k) & (M - 1))];
+        const double2 A = cadd(zk, conj2(zm)), B = csub(zk, conj2(zm));
+        const double2 Q = cmul(wv[u], B);
+        out[tile_index(k, r, rows_alloc)] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
+      }
+    }
   }
 }
 
@@ -141,14 +170,7 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * swz(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);
-  // real-input packing: X[k] = 1/2 (Z[k] + conj Z[M-k]) - i/2 w^k (Z[k] - conj Z[M-k])
-  const int rs = kRealTwN / (2 * M);
-  for (int k = t; k <= M; k += T) {
-    const double2 zk = buf[swz(k & (M - 1))], zm = buf[swz((M - k) & (M - 1))];
-    const double2 A = cadd(zk, conj2(zm)), B = csub(zk, conj2(zm));
-    const double2 Q = cmul(g_rtw[k * rs], B);
-    out[tile_index(k, r, rows_alloc)] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
-  }
+  pack_real_row(buf, M, out, r, rows_alloc);
 }
 
 // The index-axis transforms of N_t = 2 Nh points are split by one radix-2
@@ -282,10 +304,11 @@ __global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__
                                                      DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint32_t red[32];
-  __shared__ double errs[16];
+  __shared__ RowStatus rst;
   __shared__ double2 ytop;                 // Y[M]
   const int i = blockIdx.x;
   if (i >= n) return;
+  row_status_init(&rst);
   constexpr int M = 1 << LOGM;
   constexpr int Ta = M >= 16 ? M >> 4 : 1, per = M >= 16 ? 16 : M;
   constexpr int rs = kRealTwN / (2 * M);
@@ -330,36 +353,28 @@ __global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__
 #pragma unroll
     for (int j = 0; j < per; ++j) {
       const int m = t + Ta * j;
-      const double s0 = rint(v[j].x), s1 = rint(v[j].y);
-      maxerr = fmax(maxerr, fmax(fabs(v[j].x - s0), fabs(v[j].y - s1)));
-      const int64_t i0 = (int64_t)s0, i1 = (int64_t)s1;
+      double r0, r1;
+      const int64_t i0 = round_to_int(v[j].x, &r0), i1 = round_to_int(v[j].y, &r1);
+      maxerr = fmax(maxerr, fmax(fabs(v[j].x - r0), fabs(v[j].y - r1)));
+      // every true coefficient is below 2^50 in magnitude (plan constraint)
+      if (fabs(v[j].x) >= kCoefLimit || fabs(v[j].y) >= kCoefLimit) bad = 1;
       if (2 * m < NC) coef[2 * m] = i0;
       else if (i0 != 0) bad = 1;
       if (2 * m + 1 < NC) coef[2 * m + 1] = i1;
       else if (i1 != 0) bad = 1;
     }
   }
-  status_max_err(st, maxerr, errs);
-  bad = __syncthreads_or(bad);
-  if (bad && t == 0) status_or(st, ST_BOUND);
-  uint64_t* sw = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(buf) + carry_off);
-  const int NWS = carry_words(NC, w, P, W);
+  row_status_add(&rst, maxerr, bad);
+  row_status_publish(&rst, st);
+  int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
   const int row = out_reverse ? (n - 1 - i) : i;
-  carry_round_pack(coef, NC, w, P, W, sw, NWS, y + (int64_t)row * W, red);
+  carry_round_pack(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
 // ------------------------------------------------------------------ launchers
 namespace {
-// Row kernels run M/16 threads (at least 64, at most 256: M <= 4096); the
-// carry step needs at most kCarryMaxPer words per thread, which holds for
-// every admissible (P, w) because the digit count L <= M.
-int row_threads(int M, int P, int W, int L, int w) {
-  int T = M / 16;
-  if (T < 64) T = 64;
-  const int NWS = carry_words(2 * L - 1, w, P, W);
-  while (T < 256 && (NWS + T - 1) / T > kCarryMaxPer) T += 64;
-  return T;
-}
+// Row kernels run M/16 threads (at least 64, at most 256: M <= 4096).
+int row_threads(int M) { return M / 16 < 64 ? 64 : M / 16; }
 int col_threads(int Nt) { return Nt / 32 < 64 ? 64 : Nt / 32; }
 
 // Raise a kernel's dynamic-LDS limit once per (device, kernel, size) so that
@@ -397,7 +412,7 @@ hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int c
                            int gather_n, int logM, double2* out, int rows_alloc, DevStatus* st,
                            hipStream_t s) {
   const int M = 1 << logM;
-  const int T = row_threads(M, P, W, L, w);
+  const int T = row_threads(M);
   const size_t lds = sizeof(double2) * (size_t)M;
   hipError_t e = set_lds((const void*)k_rows_fwd, lds);
   if (e != hipSuccess) return e;
@@ -462,13 +477,13 @@ template <int LOGM>
 hipError_t rows_inv_t(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
                       uint64_t* y, DevStatus* st, hipStream_t s) {
   constexpr int M = 1 << LOGM;
-  const int T = row_threads(M, P, W, L, w);
+  const int T = row_threads(M);
   const int NC = 2 * L - 1;
   // FFT points during the transform; afterwards NC int64 coefficients then
   // the carry scratch
   const size_t fft_part = sizeof(double2) * (size_t)M;
   const size_t carry_off = ((size_t)NC * 8 + 15) / 16 * 16;
-  const size_t carry_part = carry_off + (size_t)carry_lds_bytes(NC, w, P, W);
+  const size_t carry_part = carry_off + (size_t)carry_lds_bytes(T);
   const size_t lds = fft_part > carry_part ? fft_part : carry_part;
   hipError_t e = set_lds((const void*)k_rows_inv<LOGM>, lds);
   if (e != hipSuccess) return e;
@@ -561,13 +576,7 @@ __device__ void b_row_fwd(const uint64_t* in, int W, int P, int w, int L, int ga
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * swz(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);
-  const int rs = kRealTwN / (2 * M);
-  for (int k = t; k <= M; k += T) {
-    const double2 zk = buf[swz(k & (M - 1))], zm = buf[swz((M - k) & (M - 1))];
-    const double2 A = cadd(zk, conj2(zm)), B = csub(zk, conj2(zm));
-    const double2 Q = cmul(g_rtw[k * rs], B);
-    out[tile_index(k, r, rows_alloc)] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
-  }
+  pack_real_row(buf, M, out, r, rows_alloc);
   __syncthreads();
 }
 
@@ -637,12 +646,26 @@ __device__ void b_col_pass(const double2* X1, const double2* Hh, int n, int logN
 __device__ void b_row_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
                           int out_reverse, uint64_t* y, int i, double2* buf, uint32_t* red,
                           DevStatus* st) {
-  __shared__ double errs[16];
+  __shared__ RowStatus rst;
   const int T = blockDim.x, t = threadIdx.x;
   const int M = 1 << logM;
   const int rs = kRealTwN / (2 * M);
   __shared__ double2 ytop;
-  for (int k = t; k < M; k += T) buf[swz(k)] = Y1[tile_index(k, i, n)];
+  row_status_init(&rst);
+  // loads four at a time per thread (clamped addresses), then LDS stores
+  for (int k0 = t; k0 < M; k0 += 4 * T) {
+    double2 ld[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * T;
+      ld[u] = Y1[tile_index(k < M ? k : 0, i, n)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = k0 + u * T;
+      if (k < M) buf[swz(k)] = ld[u];
+    }
+  }
   if (t == 0) ytop = Y1[tile_index(M, i, n)];
   __syncthreads();
   double2 z[16];
@@ -680,23 +703,22 @@ __device__ void b_row_inv(const double2* Y1, int n, int logM, int L, int w, int 
   for (int a = 0; a < 16; ++a) {
     const int m = t + a * T;
     if (m < M) {
-      const double s0 = rint(v[a].x), s1 = rint(v[a].y);
-      maxerr = fmax(maxerr, fmax(fabs(v[a].x - s0), fabs(v[a].y - s1)));
-      const int64_t i0 = (int64_t)s0, i1 = (int64_t)s1;
+      double r0, r1;
+      const int64_t i0 = round_to_int(v[a].x, &r0), i1 = round_to_int(v[a].y, &r1);
+      maxerr = fmax(maxerr, fmax(fabs(v[a].x - r0), fabs(v[a].y - r1)));
+      if (fabs(v[a].x) >= kCoefLimit || fabs(v[a].y) >= kCoefLimit) bad = 1;
       if (2 * m < NC) coef[2 * m] = i0;
       else if (i0 != 0) bad = 1;
       if (2 * m + 1 < NC) coef[2 * m + 1] = i1;
       else if (i1 != 0) bad = 1;
     }
   }
-  status_max_err(st, maxerr, errs);
-  bad = __syncthreads_or(bad);
-  if (bad && t == 0) status_or(st, ST_BOUND);
+  row_status_add(&rst, maxerr, bad);
+  row_status_publish(&rst, st);
   const int carry_off = (NC * 8 + 15) / 16 * 16;
-  uint64_t* sw = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(buf) + carry_off);
-  const int NWS = carry_words(NC, w, P, W);
+  int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
   const int row = out_reverse ? (n - 1 - i) : i;
-  carry_round_pack(coef, NC, w, P, W, sw, NWS, y + (int64_t)row * W, red);
+  carry_round_pack(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
 __global__ void __launch_bounds__(256) k_batch(const BatchInst* __restrict__ inst,
@@ -777,7 +799,7 @@ hipError_t launch_batch_phase(const BatchInst* inst, const int4* items, int nite
   const size_t lds = kBatchDynLds;
   e = set_lds((const void*)k_batch_phase, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_phase, dim3(nitems), dim3(256), lds, s, inst, items, nitems, st);
+  hipLaunchKernelGGL(k_batch_phase, dim3(nitems), dim3(kBatchThreads), lds, s, inst, items, nitems, st);
   return hipGetLastError();
 }
 
@@ -798,7 +820,7 @@ hipError_t launch_batch(const BatchInst* inst, const int4* items, int nitems, in
   const size_t lds = kBatchDynLds;
   e = set_lds((const void*)k_batch, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(256), lds, s, inst, items, nitems, head, ctr,
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBatchThreads), lds, s, inst, items, nitems, head, ctr,
                      spin_limit, st);
   return hipGetLastError();
 }

@@ -10,7 +10,9 @@ namespace hmv {
 struct DevStatus;
 
 constexpr int kMaxWords = 648;      // W for P up to 40960 is 641
-constexpr int kSchoolMaxK = 16;     // coefficients per thread in the schoolbook row kernel
+constexpr int kSchoolMaxK = 16;
+constexpr int kSchoolThreads = 512;   // work-group size of the schoolbook row kernel
+constexpr int kBatchThreads = 256;    // work-group size of the batch kernels     // coefficients per thread in the schoolbook row kernel
 
 // status block
 hipError_t launch_clear_status(DevStatus* st, hipStream_t s);

@@ -143,10 +143,9 @@ __global__ void __launch_bounds__(512) k_ntt_rows_inv(const uint64_t* __restrict
   }
   bad = __syncthreads_or(bad);
   if (bad && t == 0) status_or(st, ST_BOUND);
-  uint64_t* sw = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(nbuf) + carry_off);
-  const int NWS = carry_words(NC, w, P, W);
+  int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(nbuf) + carry_off);
   const int row = out_reverse ? (n - 1 - i) : i;
-  carry_round_pack(coef, NC, w, P, W, sw, NWS, y + (int64_t)row * W, red);
+  carry_round_pack(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
 // ------------------------------------------------------------------ columns
@@ -318,20 +317,16 @@ hipError_t nset_lds(const void* fn, size_t bytes) {
   return e;
 }
 
-int nrow_threads(int N, int P, int W, int L, int w) {
-  int T = N / 16;
-  if (T < 64) T = 64;
-  const int NWS = carry_words(2 * L - 1, w, P, W);
-  while (T < 512 && (NWS + T - 1) / T > kCarryMaxPer) T += 64;
-  return T;
-}
+// Row kernels run N/16 threads, at least 64 (the inverse kernel holds 16
+// residues per thread).
+int nrow_threads(int N) { return N / 16 < 64 ? 64 : N / 16; }
 }  // namespace
 
 hipError_t launch_ntt_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int count,
                                int gather_n, int logN, uint64_t* out, int rows_alloc, int logT,
                                DevStatus* st, hipStream_t s) {
   const int N = 1 << logN;
-  const int T = nrow_threads(N, P, W, L, w);
+  const int T = nrow_threads(N);
   const size_t lds = 8 * (size_t)N;
   hipError_t e = nset_lds((const void*)k_ntt_rows_fwd, lds);
   if (e != hipSuccess) return e;
@@ -344,10 +339,10 @@ hipError_t launch_ntt_rows_inv(const uint64_t* Y, int n, int logN, int L, int w,
                                int out_reverse, int logT, uint64_t* y, DevStatus* st,
                                hipStream_t s) {
   const int N = 1 << logN;
-  const int T = nrow_threads(N, P, W, L, w);
+  const int T = nrow_threads(N);
   const int NC = 2 * L - 1;
   const size_t carry_off = ((size_t)NC * 8 + 15) / 16 * 16;
-  size_t lds = carry_off + (size_t)carry_lds_bytes(NC, w, P, W);
+  size_t lds = carry_off + (size_t)carry_lds_bytes(T);
   if (lds < 8 * (size_t)N) lds = 8 * (size_t)N;
   hipError_t e = nset_lds((const void*)k_ntt_rows_inv, lds);
   if (e != hipSuccess) return e;

@@ -123,9 +123,10 @@ int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
     if (!fft_sizes(n, P, w, &c)) continue;
     const double nh = std::sqrt((double)hn[w - wlo]);
     const double b = fft_bound_for(c, n, nh);
-    // every true coefficient is an integer of magnitude <= n L 4^(w-1) < 2^52
+    // every true coefficient is an integer of magnitude <= n L 4^(w-1) < 2^50
+    // (the rounding step converts with a 1.5 * 2^52 offset, exact below 2^51)
     const double cmax = (double)n * c.L * std::ldexp(1.0, 2 * (w - 1));
-    if (b < 0.5 && cmax < std::ldexp(1.0, 52)) {
+    if (b < 0.5 && cmax < std::ldexp(1.0, 50)) {
       z = c;
       p->bound = b;
       p->norm_h = nh;

@@ -80,8 +80,7 @@ __global__ void __launch_bounds__(512) k_school_row(const double* __restrict__ h
   }
   __syncthreads();
   int64_t* coef = reinterpret_cast<int64_t*>(smem);
-  const int NWS = carry_words(NC, w, P, W);
-  uint64_t* sw = reinterpret_cast<uint64_t*>(coef + NC);
+  int64_t* cs = coef + NC;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int e = t + T * k;
@@ -89,13 +88,13 @@ __global__ void __launch_bounds__(512) k_school_row(const double* __restrict__ h
   }
   __syncthreads();
   const int row = out_reverse ? (n - 1 - i) : i;
-  carry_round_pack(coef, NC, w, P, W, sw, NWS, y + (int64_t)row * W, red);
+  carry_round_pack(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
 size_t school_lds_bytes(int L, int w, int P, int W) {
   const int NC = 2 * L - 1;
   const size_t a = (size_t)(2 * L + 128) * 8;
-  const size_t b = (size_t)NC * 8 + (size_t)carry_lds_bytes(NC, w, P, W);
+  const size_t b = (size_t)NC * 8 + (size_t)carry_lds_bytes(kSchoolThreads);
   return a > b ? a : b;
 }
 
@@ -116,7 +115,7 @@ hipError_t launch_school_rows(const double* hd, const double* xd, int n, int L, 
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_school_row, dim3(n), dim3(512), lds, s, hd, xd, n, L, ld, w, P, W,
+  hipLaunchKernelGGL(k_school_row, dim3(n), dim3(kSchoolThreads), lds, s, hd, xd, n, L, ld, w, P, W,
                      out_reverse, y);
   return hipGetLastError();
 }
