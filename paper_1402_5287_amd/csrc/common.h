@@ -28,36 +28,32 @@ __device__ inline void status_or(DevStatus* st, uint32_t f) {
   if (st) atomicOr(&st->flags, f);
 }
 
-// Per-row status of the rounding step: every thread folds its largest
-// rounding distance and its bound flag into two LDS slots (LDS atomics, no
-// shuffles); after one barrier thread 0 publishes them with at most one
-// global atomic each, the max-error one only when it raises the recorded
-// value (thousands of work-groups updating one word would otherwise
-// serialise on it).  Non-negative doubles order like their bit patterns.
+// Per-row status of the rounding step.  Every thread folds its largest
+// rounding distance into one of 16 LDS slots (LDS atomics on 16 addresses,
+// so at most 16 threads contend for one); the bound flag rides on the
+// barrier.  Thread 0 then publishes both with at most one global atomic
+// each, the max-error one only when it raises the recorded value (thousands
+// of work-groups updating one word would otherwise serialise on it).
+// Non-negative doubles order like their bit patterns.
 struct RowStatus {
-  unsigned long long err;
-  uint32_t bad;
+  unsigned long long err[16];
 };
-// thread 0, before the work-group's first barrier
+// before the work-group's first barrier
 __device__ inline void row_status_init(RowStatus* rs) {
-  if (threadIdx.x == 0) {
-    rs->err = 0ull;
-    rs->bad = 0u;
-  }
+  if (threadIdx.x < 16) rs->err[threadIdx.x] = 0ull;
 }
-__device__ inline void row_status_add(RowStatus* rs, double err, int bad) {
-  atomicMax(&rs->err, (unsigned long long)__double_as_longlong(err));
-  if (bad) atomicOr(&rs->bad, 1u);
-}
-// ends with a barrier
-__device__ inline void row_status_publish(RowStatus* rs, DevStatus* st) {
-  __syncthreads();
+// every thread; ends with a barrier
+__device__ __forceinline__ void row_status_publish(RowStatus* rs, double err, int bad, DevStatus* st) {
+  atomicMax(&rs->err[threadIdx.x & 15], (unsigned long long)__double_as_longlong(err));
+  bad = __syncthreads_or(bad);
   if (threadIdx.x == 0 && st) {
-    const unsigned long long bits = rs->err;
+    unsigned long long bits = rs->err[0];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) bits = rs->err[k] > bits ? rs->err[k] : bits;
     unsigned long long* dst = reinterpret_cast<unsigned long long*>(&st->max_err_bits);
     if (bits > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       atomicMax(dst, bits);
-    if (rs->bad) status_or(st, ST_BOUND);
+    if (bad) status_or(st, ST_BOUND);
   }
 }
 
@@ -67,7 +63,7 @@ constexpr double kCoefLimit = 1125899906842624.0;   // 2^50
 
 // Nearest integer of v (ties to even) for |v| < 2^51, as a double and as an
 // int64: adding 1.5 * 2^52 leaves the rounded value in the low mantissa bits.
-__device__ inline int64_t round_to_int(double v, double* rounded) {
+__device__ __forceinline__ int64_t round_to_int(double v, double* rounded) {
   const double kMagic = 6755399441055744.0;        // 1.5 * 2^52
   const double t = v + kMagic;
   *rounded = t - kMagic;
@@ -101,7 +97,7 @@ __device__ inline void load_words(const uint64_t* __restrict__ src, int W, uint6
 // again.
 // ---------------------------------------------------------------------------
 template <class Op>
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t ident, Op op, uint32_t* lds) {
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t ident, Op op, uint32_t* lds) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   uint32_t inc = v;
 #pragma unroll
@@ -177,7 +173,7 @@ __device__ inline uint32_t raw_digit(const uint64_t* wd, int W, uint64_t signw, 
 // per digit.  The balancing carry c_{e+1} = [u_e + c_e >= 2^(w-1)] is resolved
 // with a block scan of generate / propagate / kill codes.  `lds` = 32 slots.
 template <class Store>
-__device__ inline void split_balanced(const uint64_t* wd, int W, int w, int L, Store store,
+__device__ __forceinline__ void split_balanced(const uint64_t* wd, int W, int w, int L, Store store,
                                       uint32_t* lds) {
   const uint64_t signw = (wd[W - 1] >> 63) ? ~0ull : 0ull;
   const int per = (L + blockDim.x - 1) / blockDim.x;
@@ -233,7 +229,7 @@ __host__ __device__ inline int carry_lds_bytes(int T) { return 8 * T + 64; }
 // (only for very large P at small widths) runs the same passes from LDS.
 constexpr int kCarryRegs = 32;
 
-__device__ inline void carry_round_pack(int64_t* coef, int NC, int w, int P, int W, int64_t* cs,
+__device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, int P, int W, int64_t* cs,
                                         uint64_t* __restrict__ y, uint32_t* red) {
   const int T = blockDim.x, t = threadIdx.x;
   const int64_t mask = (int64_t(1) << w) - 1;

@@ -364,8 +364,7 @@ __global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__
       else if (i1 != 0) bad = 1;
     }
   }
-  row_status_add(&rst, maxerr, bad);
-  row_status_publish(&rst, st);
+  row_status_publish(&rst, maxerr, bad, st);
   int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
   const int row = out_reverse ? (n - 1 - i) : i;
   carry_round_pack(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
@@ -713,8 +712,7 @@ __device__ void b_row_inv(const double2* Y1, int n, int logM, int L, int w, int 
       else if (i1 != 0) bad = 1;
     }
   }
-  row_status_add(&rst, maxerr, bad);
-  row_status_publish(&rst, st);
+  row_status_publish(&rst, maxerr, bad, st);
   const int carry_off = (NC * 8 + 15) / 16 * 16;
   int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
   const int row = out_reverse ? (n - 1 - i) : i;
