@@ -162,7 +162,8 @@ def main():
     plan_ms = ev_a.elapsed_time(ev_b)
     info = plan.info()
     log(f"plan: w={info['w']} L={info['L']} Nt={info['Nt']} Nz={info['Nz']} "
-        f"bound={info['bound']:.3g} in {plan_ms:.1f} ms")
+        f"bound={info['bound']:.3g} variants={info.get('cols_variant')}/"
+        f"{info.get('rows_inv_variant')} in {plan_ms:.1f} ms (includes the tuning runs)")
 
     # ---- warmup
     for k in range(Wm):
@@ -305,6 +306,8 @@ def main():
                                f"{V} unit-norm x, plan once", "n": n, "P": P,
                    "algo": args.algo, "w": info["w"], "L": info["L"], "Nt": info["Nt"],
                    "Nz": info["Nz"], "bound": info["bound"], "vectors": V,
+                   "launch_variants": {"index_pass": info.get("cols_variant"),
+                                       "inverse_row_pass": info.get("rows_inv_variant")},
                    "parallelism": "single-gpu"},
         "p50_ms": round(p50, 4), "p99_ms": round(p99, 4), "plan_ms": round(plan_ms, 2),
         "max_round_err": max_err,

@@ -111,6 +111,8 @@ typedef struct {
   double norm_h;          /* Euclidean norm of the limb digits of h              */
   int64_t plan_bytes;     /* plan memory actually used                           */
   int64_t matvec_workspace_bytes;
+  int32_t cols_variant;   /* split-FFT launch variants (see hmv_autotune)        */
+  int32_t rows_inv_variant;
 } hmv_plan_info_t;
 
 int64_t hmv_plan_bytes(int kind, int64_t n, int32_t P, int algo);
@@ -129,6 +131,15 @@ int hmv_plan_matvec(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* 
 int hmv_plan_matvec_events(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* ws,
                            int64_t ws_bytes, void* stream, void* const* events);
 int64_t hmv_plan_workspace_bytes(const hmv_plan* plan);
+/* Launch tuning of the split-FFT path (on by default).  When on, planning a
+ * shape (n, P, limb width) for the first time in the process also times
+ * each launch variant of the index-axis pass (radix-16 or radix-8 register
+ * transforms; XCD-grouped or linear column order) and of the inverse limb
+ * pass (radix 16 or 8) on the plan's own data, and keeps the fastest; later
+ * plans of that shape, and one-shot calls, reuse the choice.  Every variant
+ * computes the same words.  Off: the first variant of each.  Process-wide;
+ * returns HMV_EINVAL for values other than 0 and 1.                        */
+int hmv_autotune(int32_t on);
 int hmv_plan_info(const hmv_plan* plan, hmv_plan_info_t* info);
 int hmv_plan_destroy(hmv_plan* plan);
 
@@ -202,6 +213,10 @@ int hmv_server_destroy(hmv_server* server);
 double hmv_fft_error_bound(double norm_h, double norm_x, int32_t log2_points, double beta);
 double hmv_twiddle_beta(void);
 int hmv_debug_force_width(int32_t w);
+/* tests only: plan the split-FFT path with fixed launch variants (the
+ * values of hmv_plan_info_t; a variant that does not exist for the shape
+ * falls back to variant 0 of that bit); -1, -1 restores tuning.            */
+int hmv_debug_force_variants(int32_t cols_variant, int32_t rows_inv_variant);
 /* tests only: spin limit of the dependency waits of the single-launch batch
  * driver (switched off in this build; kept for its test); 0 = default.     */
 int hmv_debug_batch_spin_limit(int32_t spins);

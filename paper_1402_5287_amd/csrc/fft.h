@@ -253,4 +253,53 @@ __device__ __forceinline__ void fft_regs(double2* v, double2* buf, int sign) {
   }
 }
 
+// The same contract with 8 elements per thread, for N = 8^P >= 64 points:
+// thread t < Ta = N/8 holds element t + Ta j in v[j]; all passes radix 8
+// (twice as many threads as fft_regs for the same N, half the registers
+// per thread).  Every thread of the block must call it.
+template <int LOGN>
+__device__ __forceinline__ void fft_regs8(double2* v, double2* buf, int sign) {
+  static_assert(LOGN % 3 == 0 && LOGN >= 6, "N must be a power of 8, at least 64");
+  constexpr int N = 1 << LOGN, Ta = N >> 3;
+  const int t = threadIdx.x;
+  const bool act = t < Ta;
+  if (act) {
+    dft<8>(v, sign);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) buf[swz(8 * t + r)] = v[r];
+  }
+  __syncthreads();
+  constexpr int NMID = LOGN / 3 - 2;
+  int Ns = 8;
+#pragma unroll
+  for (int p = 0; p < NMID; ++p) {
+    stockham_pass<8, 1>(buf, N, Ns, sign);
+    Ns <<= 3;
+  }
+  if (act) {
+    // last pass, span N/8: butterfly t writes elements t + Ta r, natural order
+    const double2* tw = g_tw + tw_offset(8, Ta);
+    double2 u[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) u[r] = buf[swz(t + r * Ta)];
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+      double2 w = tw[t * 7 + (r - 1)];
+      if (sign > 0) w.y = -w.y;
+      u[r] = cmul(u[r], w);
+    }
+    dft<8>(u, sign);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = u[r];
+  }
+  __syncthreads();
+}
+
+// fft_regs (R = 16 elements per thread) or fft_regs8 (R = 8).
+template <int LOGN, int R>
+__device__ __forceinline__ void fft_regs_r(double2* v, double2* buf, int sign) {
+  if constexpr (R == 8) fft_regs8<LOGN>(v, buf, sign);
+  else fft_regs<LOGN>(v, buf, sign);
+}
+
 }  // namespace hmv

@@ -7,20 +7,23 @@
 namespace hmv {
 
 // ---------------------------------------------------------------- twiddles
-// One table per (R, Ns), R in {2,4,8,16}, Ns in {1,16,256,4096}:
+// One table per (R, Ns), R in {2,4,8,16}, Ns in {1,8,16,64,256,512,4096}
+// (the spans of radix-16 passes and of radix-8 passes):
 // entries [k][r-1] = exp(-2 pi i r k / (R Ns)), k < Ns, 1 <= r < R.
+constexpr int kTwSpans = 7;
+__host__ __device__ constexpr int tw_span(int b) {
+  return b == 0 ? 1 : b == 1 ? 8 : b == 2 ? 16 : b == 3 ? 64 : b == 4 ? 256 : b == 5 ? 512 : 4096;
+}
 __host__ __device__ constexpr int64_t tw_offset(int R, int Ns) {
   int64_t off = 0;
-  const int radices[4] = {2, 4, 8, 16};
-  const int spans[4] = {1, 16, 256, 4096};
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) {
-      if (radices[a] == R && spans[b] == Ns) return off;
-      off += (int64_t)spans[b] * (radices[a] - 1);
+  for (int a = 1; a <= 4; ++a)
+    for (int b = 0; b < kTwSpans; ++b) {
+      if ((1 << a) == R && tw_span(b) == Ns) return off;
+      off += (int64_t)tw_span(b) * ((1 << a) - 1);
     }
   return off;
 }
-constexpr int64_t kTwEntries = (1 + 3 + 7 + 15) * (1 + 16 + 256 + 4096);
+constexpr int64_t kTwEntries = (1 + 3 + 7 + 15) * (1 + 8 + 16 + 64 + 256 + 512 + 4096);
 // real-input packing roots exp(-2 pi i k / 16384), k = 0..8192
 constexpr int kRealTwN = 16384;
 constexpr int64_t kRealTwEntries = kRealTwN / 2 + 1;

@@ -230,15 +230,20 @@ __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H
 // Column pass of the matvec: x column reversed (x_hat[s] = x[n-1-s], zero for
 // s >= n; n <= Nh so the high half is zero), forward transform, times the
 // resident spectrum of h, inverse transform, keep rows n-1 .. 2n-2.
-template <int LOGNH>
-__global__ void __launch_bounds__(512) k_cols_pass(const double2* __restrict__ X1,
-                                                   const double2* __restrict__ Hh, int n, int C,
-                                                   double2* __restrict__ Y1) {
+// Variants (picked per shape by the planner's tuning runs): R = elements per
+// thread of the register-resident transforms (16, or 8 with twice the
+// threads and at most 128 VGPRs so that four waves fit per SIMD; the radix-8
+// form reloads the column for the odd half instead of keeping it), and the
+// column order (XCD-grouped or linear).
+template <int LOGNH, int R>
+__global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
+    const double2* __restrict__ X1, const double2* __restrict__ Hh, int n, int C, int linear,
+    double2* __restrict__ Y1) {
   extern __shared__ double2 buf[];
-  const int c = xcd_slot(blockIdx.x, gridDim.x);
+  const int c = linear ? (int)blockIdx.x : xcd_slot(blockIdx.x, gridDim.x);
   if (c >= C) return;
   constexpr int logNt = LOGNH + 1, Nh = 1 << LOGNH;
-  constexpr int Ta = Nh >= 16 ? Nh >> 4 : 1, per = Nh >= 16 ? 16 : Nh;
+  constexpr int Ta = Nh >= R ? Nh / R : 1, per = Nh >= R ? R : Nh;
   constexpr int rs = kRealTwN >> logNt;
   const int t = threadIdx.x;
   const bool act = t < Ta;
@@ -246,39 +251,46 @@ __global__ void __launch_bounds__(512) k_cols_pass(const double2* __restrict__ X
   const double2* he = Hh + (int64_t)c * (2 * Nh);
   const double2* ho = he + Nh;
   double2* ycol = Y1 + tile_index(c, 0, n);
-  // The column is read from HBM once: v carries the even half, o keeps the
-  // input for the odd half (its registers are live in the odd half anyway).
   // Every per-element loop sits in one guarded block with in-bounds
   // (clamped) addresses, so its loads are issued together rather than one
-  // round trip per element.
-  double2 v[16], o[16];
+  // round trip per element.  With R = 16 the column is read from HBM once:
+  // v carries the even half, o keeps the input for the odd half (its
+  // registers are live in the odd half anyway).
+  double2 v[R], o[R];
   if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
       const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * 8];
       v[j] = s < n ? xv : make_double2(0.0, 0.0);
-      o[j] = v[j];
+      if constexpr (R == 16) o[j] = v[j];
     }
   }
   // even frequencies
-  fft_regs<LOGNH>(v, buf, -1);
+  fft_regs_r<LOGNH, R>(v, buf, -1);
   if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) v[j] = cmul(v[j], he[t + Ta * j]);
   }
-  fft_regs<LOGNH>(v, buf, +1);
+  fft_regs_r<LOGNH, R>(v, buf, +1);
   // odd frequencies
   if (act) {
 #pragma unroll
-    for (int j = 0; j < per; ++j) o[j] = cmul(o[j], g_rtw[(t + Ta * j) * rs]);
+    for (int j = 0; j < per; ++j) {
+      const int s = t + Ta * j;
+      if constexpr (R != 16) {
+        const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * 8];
+        o[j] = s < n ? xv : make_double2(0.0, 0.0);
+      }
+      o[j] = cmul(o[j], g_rtw[s * rs]);
+    }
   }
-  fft_regs<LOGNH>(o, buf, -1);
+  fft_regs_r<LOGNH, R>(o, buf, -1);
   if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) o[j] = cmul(o[j], ho[t + Ta * j]);
   }
-  fft_regs<LOGNH>(o, buf, +1);
+  fft_regs_r<LOGNH, R>(o, buf, +1);
   // recombine and keep the window
   if (act) {
 #pragma unroll
@@ -297,11 +309,12 @@ __global__ void __launch_bounds__(512) k_cols_pass(const double2* __restrict__ X
 // last FFT pass leaves the coefficients in registers, where they are rounded
 // and then stored compactly (coefficient e in int64 slot e) at the start of
 // the FFT buffer; the carry scratch follows at carry_off.
-template <int LOGM>
-__global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__ Y1, int n, int L,
-                                                     int w, int P, int W, int out_reverse,
-                                                     int carry_off, uint64_t* __restrict__ y,
-                                                     DevStatus* st) {
+// R = elements per thread of the inverse transform (16, or 8 with twice the
+// threads at four waves per SIMD), picked per shape by the tuning runs.
+template <int LOGM, int R>
+__global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
+    const double2* __restrict__ Y1, int n, int L, int w, int P, int W, int out_reverse,
+    int carry_off, uint64_t* __restrict__ y, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint32_t red[32];
   __shared__ RowStatus rst;
@@ -310,13 +323,13 @@ __global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__
   if (i >= n) return;
   row_status_init(&rst);
   constexpr int M = 1 << LOGM;
-  constexpr int Ta = M >= 16 ? M >> 4 : 1, per = M >= 16 ? 16 : M;
+  constexpr int Ta = M >= R ? M / R : 1, per = M >= R ? R : M;
   constexpr int rs = kRealTwN / (2 * M);
   const int t = threadIdx.x;
   const bool act = t < Ta;
   // the row and the packing roots, all loads in flight together (one
   // guarded block; element k = t + Ta j covers every k < M)
-  double2 wk[16], v[16];
+  double2 wk[R], v[R];
   const double2 top = Y1[tile_index(M, i, n)];
   if (act) {
 #pragma unroll
@@ -343,7 +356,7 @@ __global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__
     }
   }
   __syncthreads();
-  fft_regs<LOGM>(v, buf, +1);
+  fft_regs_r<LOGM, R>(v, buf, +1);
   // element m = t + Ta j holds coefficients 2m (real part) and 2m+1 (imaginary)
   int64_t* coef = reinterpret_cast<int64_t*>(buf);
   const int NC = 2 * L - 1;
@@ -372,9 +385,11 @@ __global__ void __launch_bounds__(256, 2) k_rows_inv(const double2* __restrict__
 
 // ------------------------------------------------------------------ launchers
 namespace {
-// Row kernels run M/16 threads (at least 64, at most 256: M <= 4096).
-int row_threads(int M) { return M / 16 < 64 ? 64 : M / 16; }
-int col_threads(int Nt) { return Nt / 32 < 64 ? 64 : Nt / 32; }
+// Work-group size of an N-point transform with R elements per thread: N/R
+// threads, at least 64.
+int fft_threads(int N, int R) { return N / R < 64 ? 64 : N / R; }
+// The radix-8 variants exist for 8^k points.
+constexpr bool has_radix8(int logn) { return logn == 6 || logn == 9 || logn == 12; }
 
 // Raise a kernel's dynamic-LDS limit once per (device, kernel, size) so that
 // later launches (possibly under stream capture) make no attribute calls.
@@ -411,7 +426,7 @@ hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int c
                            int gather_n, int logM, double2* out, int rows_alloc, DevStatus* st,
                            hipStream_t s) {
   const int M = 1 << logM;
-  const int T = row_threads(M);
+  const int T = fft_threads(M, 16);           // the LDS transform needs N/16 threads
   const size_t lds = sizeof(double2) * (size_t)M;
   hipError_t e = set_lds((const void*)k_rows_fwd, lds);
   if (e != hipSuccess) return e;
@@ -427,21 +442,33 @@ hipError_t cols_plan_t(const double2* H1, int rows, int C, double scale, double2
   hipError_t e = set_lds((const void*)k_cols_plan<LOGNH>, lds);
   if (e != hipSuccess) return e;
   const int grid = (C + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_cols_plan<LOGNH>, dim3(grid), dim3(col_threads(2 << LOGNH)), lds, s, H1,
+  hipLaunchKernelGGL(k_cols_plan<LOGNH>, dim3(grid), dim3(fft_threads(1 << LOGNH, 16)), lds, s, H1,
                      rows, C, scale, Hh);
   return hipGetLastError();
 }
 
-template <int LOGNH>
-hipError_t cols_pass_t(const double2* X1, const double2* Hh, int n, int C, double2* Y1,
-                       hipStream_t s) {
+template <int LOGNH, int R>
+hipError_t cols_pass_r(const double2* X1, const double2* Hh, int n, int C, int linear,
+                       double2* Y1, hipStream_t s) {
   const size_t lds = sizeof(double2) * (size_t)(1 << LOGNH);
-  hipError_t e = set_lds((const void*)k_cols_pass<LOGNH>, lds);
+  hipError_t e = set_lds((const void*)k_cols_pass<LOGNH, R>, lds);
   if (e != hipSuccess) return e;
   const int grid = (C + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_cols_pass<LOGNH>, dim3(grid), dim3(col_threads(2 << LOGNH)), lds, s, X1,
-                     Hh, n, C, Y1);
+  hipLaunchKernelGGL((k_cols_pass<LOGNH, R>), dim3(grid), dim3(fft_threads(1 << LOGNH, R)), lds,
+                     s, X1, Hh, n, C, linear, Y1);
   return hipGetLastError();
+}
+
+// variant: bit 0 = radix-8 transforms (where they exist), bit 1 = linear
+// column order
+template <int LOGNH>
+hipError_t cols_pass_t(const double2* X1, const double2* Hh, int n, int C, int variant,
+                       double2* Y1, hipStream_t s) {
+  const int linear = (variant >> 1) & 1;
+  if constexpr (has_radix8(LOGNH)) {
+    if (variant & 1) return cols_pass_r<LOGNH, 8>(X1, Hh, n, C, linear, Y1, s);
+  }
+  return cols_pass_r<LOGNH, 16>(X1, Hh, n, C, linear, Y1, s);
 }
 
 #define HMV_NT_DISPATCH(FN, ...)                  \
@@ -468,15 +495,15 @@ hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, doubl
 }
 
 hipError_t launch_cols_pass(const double2* X1, const double2* Hh, int n, int C, int logNt,
-                            double2* Y1, hipStream_t s) {
-  HMV_NT_DISPATCH(cols_pass_t, X1, Hh, n, C, Y1, s)
+                            double2* Y1, int variant, hipStream_t s) {
+  HMV_NT_DISPATCH(cols_pass_t, X1, Hh, n, C, variant, Y1, s)
 }
 
-template <int LOGM>
-hipError_t rows_inv_t(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
+template <int LOGM, int R>
+hipError_t rows_inv_r(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
                       uint64_t* y, DevStatus* st, hipStream_t s) {
   constexpr int M = 1 << LOGM;
-  const int T = row_threads(M);
+  const int T = fft_threads(M, R);
   const int NC = 2 * L - 1;
   // FFT points during the transform; afterwards NC int64 coefficients then
   // the carry scratch
@@ -484,18 +511,29 @@ hipError_t rows_inv_t(const double2* Y1, int n, int L, int w, int P, int W, int 
   const size_t carry_off = ((size_t)NC * 8 + 15) / 16 * 16;
   const size_t carry_part = carry_off + (size_t)carry_lds_bytes(T);
   const size_t lds = fft_part > carry_part ? fft_part : carry_part;
-  hipError_t e = set_lds((const void*)k_rows_inv<LOGM>, lds);
+  hipError_t e = set_lds((const void*)k_rows_inv<LOGM, R>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rows_inv<LOGM>, dim3(n), dim3(T), lds, s, Y1, n, L, w, P, W, out_reverse,
-                     (int)carry_off, y, st);
+  hipLaunchKernelGGL((k_rows_inv<LOGM, R>), dim3(n), dim3(T), lds, s, Y1, n, L, w, P, W,
+                     out_reverse, (int)carry_off, y, st);
   return hipGetLastError();
 }
 
+// variant: bit 0 = radix-8 transform (where it exists)
+template <int LOGM>
+hipError_t rows_inv_t(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
+                      uint64_t* y, DevStatus* st, int variant, hipStream_t s) {
+  if constexpr (has_radix8(LOGM)) {
+    if (variant & 1) return rows_inv_r<LOGM, 8>(Y1, n, L, w, P, W, out_reverse, y, st, s);
+  }
+  return rows_inv_r<LOGM, 16>(Y1, n, L, w, P, W, out_reverse, y, st, s);
+}
+
 hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
-                           int out_reverse, uint64_t* y, DevStatus* st, hipStream_t s) {
+                           int out_reverse, uint64_t* y, DevStatus* st, int variant,
+                           hipStream_t s) {
   switch (logM) {
 #define HMV_RI(k) \
-  case k: return rows_inv_t<k>(Y1, n, L, w, P, W, out_reverse, y, st, s);
+  case k: return rows_inv_t<k>(Y1, n, L, w, P, W, out_reverse, y, st, variant, s);
     HMV_RI(1) HMV_RI(2) HMV_RI(3) HMV_RI(4) HMV_RI(5) HMV_RI(6) HMV_RI(7) HMV_RI(8) HMV_RI(9)
     HMV_RI(10) HMV_RI(11) HMV_RI(12)
 #undef HMV_RI

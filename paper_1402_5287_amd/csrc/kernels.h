@@ -39,10 +39,14 @@ hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int c
                            hipStream_t s);
 hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, double scale,
                             double2* Hh, hipStream_t s);
+// variant bit 0: radix-8 register transforms (where they exist, 8^k points);
+// bit 1 (column pass only): linear instead of XCD-grouped column order.
+constexpr int kColsVariants = 4, kRowsInvVariants = 2;
 hipError_t launch_cols_pass(const double2* X1, const double2* Hh, int n, int C, int logNt,
-                            double2* Y1, hipStream_t s);
+                            double2* Y1, int variant, hipStream_t s);
 hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
-                           int out_reverse, uint64_t* y, DevStatus* st, hipStream_t s);
+                           int out_reverse, uint64_t* y, DevStatus* st, int variant,
+                           hipStream_t s);
 
 }  // namespace hmv
 

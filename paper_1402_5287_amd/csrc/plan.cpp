@@ -8,7 +8,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 
 #include "common.h"
 #include "hmv.h"
@@ -43,8 +46,11 @@ bool fft_sizes(int64_t n, int32_t P, int w, FftSizes* z) {
   z->C = (int)(z->Nz / 2 + 1);
   z->tiles = (z->C + 7) / 8;
   z->plan_bytes = align_up(16 * int64_t(z->C) * z->Nt);
-  // plan scratch: limb-norm counters + the row spectra of h
-  z->plan_scratch = align_up(kNormSlots * 8) + align_up(16 * 8 * int64_t(z->tiles) * (2 * n - 1));
+  // plan scratch: limb-norm counters + the row spectra of h; the tuning runs
+  // reuse it as row spectra of x and of y (n rows each)
+  const int64_t h_rows = align_up(16 * 8 * int64_t(z->tiles) * (2 * n - 1));
+  const int64_t xy_rows = 2 * align_up(16 * 8 * int64_t(z->tiles) * n);
+  z->plan_scratch = align_up(kNormSlots * 8) + (h_rows > xy_rows ? h_rows : xy_rows);
   // matvec scratch: row spectra of x and of y
   z->mv_scratch = 2 * align_up(16 * 8 * int64_t(z->tiles) * n);
   return true;
@@ -78,6 +84,86 @@ double fft_bound_for(const FftSizes& z, int64_t n, double norm_h) {
 
 // ------------------------------------------------------------------ split-FFT
 namespace {
+
+// Launch-variant tuning.  For each shape the planner times every variant of
+// the column pass and of the inverse row pass (kernels.h) on the plan's own
+// data and keeps the fastest; results are cached per (device, n, P, w), so
+// later plans of a shape (and one-shot calls) reuse them.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int64_t, int32_t, int>, std::pair<int, int>> g_tune_cache;
+int g_autotune = 1;
+int g_force_cols = -1, g_force_rinv = -1;       // tests: fixed variants (-1 = tune)
+
+bool radix8_ok(int logn) { return logn == 6 || logn == 9 || logn == 12; }
+
+// Average time of `reps` launches after one warm-up, in milliseconds.
+template <class F>
+hipError_t time_launches(F launch, int reps, hipEvent_t a, hipEvent_t b, hipStream_t s,
+                         float* ms) {
+  hipError_t e = launch();
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, a, b);
+  if (e == hipSuccess) *ms /= (float)reps;
+  return e;
+}
+
+// Times the variants with the row spectra of h (first n rows of the plan
+// scratch) as x's spectra; the outputs are discarded and the status block
+// is cleared afterwards.
+int fft_tune(hmv_plan* p, DevStatus* st, char* scratch, hipStream_t s) {
+  const std::tuple<int, int64_t, int32_t, int> key{p->device, p->n, p->P, p->w};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      p->cols_variant = it->second.first;
+      p->rows_inv_variant = it->second.second;
+      return HMV_OK;
+    }
+  }
+  const int n = (int)p->n, W = (int)words_of(p->P);
+  double2* X1 = reinterpret_cast<double2*>(scratch + align_up(kNormSlots * 8));
+  double2* Y1 = X1 + align_up(16 * 8 * int64_t(p->tiles) * n) / 16;
+  uint64_t* yt = reinterpret_cast<uint64_t*>(X1);      // x's spectra are no longer needed then
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  int bc = 0, br = 0;
+  float best = 0.0f;
+  for (int v = 0; v < kColsVariants && e == hipSuccess; ++v) {
+    if ((v & 1) && !radix8_ok(p->logNt - 1)) continue;
+    float ms = 0.0f;
+    e = time_launches([&] { return launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, Y1, v, s); },
+                      2, a, b, s, &ms);
+    if (e == hipSuccess && (v == 0 || ms < best)) {
+      best = ms;
+      bc = v;
+    }
+  }
+  for (int v = 0; v < kRowsInvVariants && e == hipSuccess; ++v) {
+    if ((v & 1) && !radix8_ok(p->logM)) continue;
+    float ms = 0.0f;
+    e = time_launches(
+        [&] { return launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, 0, yt, st, v, s); }, 2,
+        a, b, s, &ms);
+    if (e == hipSuccess && (v == 0 || ms < best)) {
+      best = ms;
+      br = v;
+    }
+  }
+  if (e == hipSuccess) e = launch_clear_status(st, s);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e != hipSuccess) return status_from_hip(e, "tuning runs");
+  p->cols_variant = bc;
+  p->rows_inv_variant = br;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = {bc, br};
+  return HMV_OK;
+}
 
 int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
                    int64_t scratch_bytes, char* plan_mem, int64_t plan_bytes, int force_w,
@@ -155,6 +241,13 @@ int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
   const double scale = std::ldexp(1.0, -(z.logNt + z.logM + 1));
   e = launch_cols_plan(H1, rows, z.C, z.logNt, scale, p->Hh, s);
   if (e != hipSuccess) return status_from_hip(e, "cols plan");
+  // 4. launch variants for this shape (h's spectra stand in for x's)
+  if (g_force_cols >= 0 || g_force_rinv >= 0) {
+    p->cols_variant = g_force_cols >= 0 ? g_force_cols : 0;
+    p->rows_inv_variant = g_force_rinv >= 0 ? g_force_rinv : 0;
+    return HMV_OK;
+  }
+  if (g_autotune) return fft_tune(p, st, scratch, s);
   return HMV_OK;
 }
 
@@ -174,11 +267,12 @@ int fft_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus
   if (e == hipSuccess) e = launch_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, st, s);
   if (e != hipSuccess) return status_from_hip(e, "rows fwd (x)");
   e = mark(ev, 1, s);
-  if (e == hipSuccess) e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, Y1, s);
+  if (e == hipSuccess) e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, Y1, p->cols_variant, s);
   if (e != hipSuccess) return status_from_hip(e, "cols pass");
   const int rev = (p->kind == HMV_HANKEL) ? 0 : 1;
   e = mark(ev, 2, s);
-  if (e == hipSuccess) e = launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, rev, y, st, s);
+  if (e == hipSuccess)
+    e = launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, rev, y, st, p->rows_inv_variant, s);
   if (e == hipSuccess) e = mark(ev, 3, s);
   return status_from_hip(e, "rows inv");
 }
@@ -641,6 +735,23 @@ int hmv_plan_info(const hmv_plan* p, hmv_plan_info_t* info) {
   info->norm_h = p->norm_h;
   info->plan_bytes = p->plan_bytes_used;
   info->matvec_workspace_bytes = kStatusBytes + p->mv_scratch;
+  info->cols_variant = p->cols_variant;
+  info->rows_inv_variant = p->rows_inv_variant;
+  return HMV_OK;
+}
+
+int hmv_debug_force_variants(int32_t cols_variant, int32_t rows_inv_variant) {
+  if (cols_variant < -1 || cols_variant >= kColsVariants || rows_inv_variant < -1 ||
+      rows_inv_variant >= kRowsInvVariants)
+    return HMV_EINVAL;
+  g_force_cols = cols_variant;
+  g_force_rinv = rows_inv_variant;
+  return HMV_OK;
+}
+
+int hmv_autotune(int32_t on) {
+  if (on != 0 && on != 1) return HMV_EINVAL;
+  g_autotune = on;
   return HMV_OK;
 }
 

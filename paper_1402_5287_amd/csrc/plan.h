@@ -77,6 +77,7 @@ struct hmv_plan {
   double bound = 0.0, beta = 0.0, norm_h = 0.0;
   int64_t plan_bytes_used = 0, mv_scratch = 0;
   double2* Hh = nullptr;           // resident spectrum of h (in caller plan memory)
+  int cols_variant = 0, rows_inv_variant = 0;   // launch variants picked by the tuning runs
   // exact paths
   int logNz = 0;
   int64_t cols_padded = 0;

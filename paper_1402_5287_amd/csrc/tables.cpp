@@ -58,11 +58,9 @@ double gen_fft_tables(double* tw, double* rtw) {
     rtw[2 * k + 1] = im;
     track(k, kRealTwN, re, im);
   }
-  const int radices[4] = {2, 4, 8, 16};
-  const int spans[4] = {1, 16, 256, 4096};
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) {
-      const int R = radices[a], Ns = spans[b];
+  for (int a = 1; a <= 4; ++a)
+    for (int b = 0; b < kTwSpans; ++b) {
+      const int R = 1 << a, Ns = tw_span(b);
       double* t = tw + 2 * tw_offset(R, Ns);
       for (int k = 0; k < Ns; ++k)
         for (int r = 1; r < R; ++r) {

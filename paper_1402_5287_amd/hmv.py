@@ -39,6 +39,8 @@ SIGNATURES = {
     "hmv_plan_h": (_c_int, [ctypes.POINTER(_vp), _c_int, _vp, _c_i64, _c_i32, _c_int, _vp, _c_i64,
                             _vp, _c_i64, _vp]),
     "hmv_plan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp]),
+    "hmv_debug_force_variants": (_c_int, [_c_i32, _c_i32]),
+    "hmv_autotune": (_c_int, [_c_i32]),
     "hmv_plan_workspace_bytes": (_c_i64, [_vp]),
     "hmv_plan_matvec_events": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp, ctypes.POINTER(_vp)]),
     "hmv_plan_info": (_c_int, [_vp, _vp]),
@@ -78,7 +80,8 @@ class PlanInfo(ctypes.Structure):
                 ("P", ctypes.c_int32), ("w", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("Nt", ctypes.c_int64), ("Nz", ctypes.c_int64), ("bound", ctypes.c_double),
                 ("beta", ctypes.c_double), ("norm_h", ctypes.c_double),
-                ("plan_bytes", ctypes.c_int64), ("matvec_workspace_bytes", ctypes.c_int64)]
+                ("plan_bytes", ctypes.c_int64), ("matvec_workspace_bytes", ctypes.c_int64),
+                ("cols_variant", ctypes.c_int32), ("rows_inv_variant", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -245,6 +248,16 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(on: bool) -> None:
+    """Launch-variant tuning at plan time (on by default; process-wide)."""
+    _check(lib().hmv_autotune(1 if on else 0), "autotune")
+
+
+def force_variants(cols: int = -1, rows_inv: int = -1) -> None:
+    """Tests only: fixed split-FFT launch variants (-1, -1 = tune)."""
+    _check(lib().hmv_debug_force_variants(cols, rows_inv), "force_variants")
 
 
 def force_width(w: int) -> None:

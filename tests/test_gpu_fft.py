@@ -154,3 +154,88 @@ def test_index_axis_16384():
         assert np.array_equal(y, kronecker.hankel_matvec_words(h, x, P))
     yt, rc, _, _ = _oneshot("toeplitz", h, x, n, P)
     assert np.array_equal(yt, y[::-1])
+
+
+def test_index_axis_8192_ragged_all_kinds():
+    """2048 < n < 4096: an 8192-point index axis with a ragged window, every
+    kind, against the exact GMP product (and sampled schoolbook rows)."""
+    need_gpu()
+    n, P = 3001, 700
+    h = si.uniform(2 * n - 1, P, (70,))
+    x = si.uniform(n, P, (71,))
+    announce("fft Nt=8192", n, P)
+    y, rc, flags, _ = _oneshot("hankel", h, x, n, P)
+    assert rc == 0 and flags == 0
+    _sampled_rows_check(h, x, y, P, [0, 1, 1500, 2999, 3000])
+    if kronecker.available():
+        assert np.array_equal(y, kronecker.hankel_matvec_words(h, x, P))
+    yt, rc, _, _ = _oneshot("toeplitz", h, x, n, P)
+    assert rc == 0 and np.array_equal(yt, y[::-1])
+    c = h[:n].copy()
+    yc, rc, _, _ = _oneshot("circulant", c, x, n, P)
+    assert rc == 0
+    rows = [0, 7, 3000]
+    want = hankel.matvec_rows("circulant", fp.decode(c), fp.decode(x), P, rows, processes=8)
+    assert fp.decode(yc[rows]) == want
+
+
+def test_planned_session_equals_exact_product():
+    """The planned path at the session shape (n = 4096, P = 33220, unit-norm
+    x): two consecutive matvecs on one plan, each equal to the GMP product."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    if not kronecker.available():
+        pytest.skip("GMP not available for the full-vector check")
+    n, P = 4096, 33220
+    h = si.session_h(n, P)
+    plan = hmv.Plan("hankel", hmv.to_device(h), n, P, algo="split_fft")
+    for k in range(2):
+        x = si.session_x(n, P, k)
+        announce("fft session", n, P, k)
+        y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+        plan.matvec(hmv.to_device(x), y)
+        rc, flags, err = hmv.read_status(plan.ws)
+        assert rc == 0 and flags == 0 and err < 0.25
+        assert np.array_equal(hmv.to_host(y), kronecker.hankel_matvec_words(h, x, P))
+    plan.close()
+
+
+@pytest.mark.parametrize("n,P", [(40, 700), (300, 2000), (3001, 700), (1000, 33220)])
+def test_every_launch_variant_is_exact(n, P):
+    """Each launch variant the tuner may pick (radix-16 or radix-8 register
+    transforms, XCD-grouped or linear columns) gives the exact words; the
+    shapes cover 64-, 512- and 4096-point index halves and limb transforms."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    h = si.uniform(2 * n - 1, P, (72, n))
+    x = si.uniform(n, P, (73, n))
+    hd, xd = hmv.to_device(h), hmv.to_device(x)
+    if n <= 300:
+        want = hankel.matvec_words("hankel", h, x, P)
+    elif kronecker.available():
+        want = kronecker.hankel_matvec_words(h, x, P)
+    else:
+        pytest.skip("GMP not available for the full-vector check")
+    try:
+        for cv in range(4):
+            for rv in range(2):
+                hmv.force_variants(cv, rv)
+                plan = hmv.Plan("hankel", hd, n, P, algo="split_fft")
+                info = plan.info()
+                announce("fft variant", n, P, cv, rv, info["w"], info["Nt"], info["Nz"])
+                y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+                plan.matvec(xd, y)
+                rc, flags, _ = hmv.read_status(plan.ws)
+                assert rc == 0 and flags == 0
+                assert np.array_equal(hmv.to_host(y), want), (cv, rv)
+                plan.close()
+    finally:
+        hmv.force_variants(-1, -1)
+    hmv.autotune(True)
+    plan = hmv.Plan("hankel", hd, n, P, algo="split_fft")
+    info = plan.info()
+    print("tuned variants", info["cols_variant"], info["rows_inv_variant"], flush=True)
+    y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+    plan.matvec(xd, y)
+    assert np.array_equal(hmv.to_host(y), want)
+    plan.close()
