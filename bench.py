@@ -468,7 +468,7 @@ def section_batch(dev, count=256, reps=3):
     sms = _ms_between(e0, e1)
     equal = all(torch.equal(o, it[3]) for o, it in zip(outs, items))
     rc, flags, _ = hmv.read_status(ws)
-    res = {"instances": count, "launches": 4, "batch_ms": round(bms, 3),
+    res = {"instances": count, "launches": hmv.batch_launches(probs), "batch_ms": round(bms, 3),
            "products_per_s": round(count / (bms * 1e-3), 1),
            "one_by_one_ms": round(sms, 3), "equal_to_single_path": bool(equal),
            "status_flags": flags,

@@ -144,18 +144,20 @@ int hmv_plan_info(const hmv_plan* plan, hmv_plan_info_t* info);
 int hmv_plan_destroy(hmv_plan* plan);
 
 /* ---------------------------------------------------------------- batches
- * Many independent products (any mix of kinds, n and P) in four launches,
- * one per pass (forward limb transforms of all h and x rows; index-axis
- * transforms of all h columns; index-axis passes of all x columns; inverse
- * limb transforms with carry of all output rows); each launch walks a device
- * list of the work items of that pass over every instance, one item per
- * work-group, with no host round trip in between.  Every instance runs the
- * split-FFT path unplanned, with its limb width taken from the worst-case
- * bound (no data-dependent read back).  Limits: n <= 2048 per instance.
- * The descriptor array is host memory; h, x, y are device pointers.  The call
- * synchronises `stream` once, after uploading its work list and before the
- * launch; the products are ready when the stream synchronises again.
- * ws (hmv_batch_workspace_bytes) starts with the 256-byte status block.   */
+ * Many independent products (any mix of kinds, n and P).  The work of all
+ * instances is cut into items of four passes: forward limb transforms of
+ * every h and x row; index-axis transforms of every h column; index-axis
+ * passes of every x column; inverse limb transforms with carry of every
+ * output row.  One launch covers the items of one pass whose transforms
+ * have the same size (hmv_batch_launches counts them), one item per
+ * work-group, with the LDS and threads of that size and no host round trip
+ * in between.  Every instance runs the split-FFT path unplanned, with its
+ * limb width taken from the worst-case bound (no data-dependent read back).
+ * Limits: n <= 2048 per instance.  The descriptor array is host memory; h,
+ * x, y are device pointers.  The call synchronises `stream` once, after
+ * uploading its work list and before the launches; the products are ready
+ * when the stream synchronises again.  ws (hmv_batch_workspace_bytes)
+ * starts with the 256-byte status block.                                  */
 typedef struct {
   int32_t kind;           /* HMV_HANKEL / HMV_TOEPLITZ / HMV_CIRCULANT                 */
   int32_t P;
@@ -168,6 +170,8 @@ typedef struct {
 int64_t hmv_batch_workspace_bytes(const hmv_problem* probs, int32_t count);
 int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t ws_bytes,
                      void* stream);
+/* Number of kernel launches hmv_batch_matvec makes for these problems. */
+int32_t hmv_batch_launches(const hmv_problem* probs, int32_t count);
 
 /* ---------------------------------------------------------------- serving
  * A request scheduler for sessions of planned matvecs (continuous

@@ -143,27 +143,31 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
     b.reverse = pr.kind == HMV_HANKEL ? 0 : 1;
     b.scale = std::ldexp(1.0, -(z.logNt + z.logM + 1));
   }
-  // work items, phase-major; within a phase the largest instances first
+  // work items, phase-major; within a pass grouped by transform size (one
+  // launch per size), largest first
   std::vector<int> order(count);
   std::iota(order.begin(), order.end(), 0);
-  std::sort(order.begin(), order.end(), [&](int a, int b) {
-    return (int64_t)probs[a].n * L.ip[a].z.C > (int64_t)probs[b].n * L.ip[b].z.C;
-  });
   std::vector<int4> items;
   items.reserve(L.nitems);
-  int phase_count[4] = {0, 0, 0, 0};
-  for (int i : order)
-    for (int r = 0; r < 3 * (int)probs[i].n - 1; ++r) items.push_back(make_int4(i, 0, r, 0));
-  phase_count[0] = (int)items.size();
-  for (int i : order)
-    for (int c = 0; c < L.ip[i].z.C; ++c) items.push_back(make_int4(i, 1, c, 0));
-  phase_count[1] = (int)items.size() - phase_count[0];
-  for (int i : order)
-    for (int c = 0; c < L.ip[i].z.C; ++c) items.push_back(make_int4(i, 2, c, 0));
-  phase_count[2] = (int)items.size() - phase_count[0] - phase_count[1];
-  for (int i : order)
-    for (int r = 0; r < (int)probs[i].n; ++r) items.push_back(make_int4(i, 3, r, 0));
-  phase_count[3] = (int)items.size() - phase_count[0] - phase_count[1] - phase_count[2];
+  struct Run { int phase, logn, start, count; };
+  std::vector<Run> runs;
+  for (int ph = 0; ph < 4; ++ph) {
+    auto logn_of = [&](int i) { return (ph == 0 || ph == 3) ? L.ip[i].z.logM : L.ip[i].z.logNt - 1; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      if (logn_of(a) != logn_of(b)) return logn_of(a) > logn_of(b);
+      return (int64_t)probs[a].n * L.ip[a].z.C > (int64_t)probs[b].n * L.ip[b].z.C;
+    });
+    for (int i : order) {
+      const int logn = logn_of(i);
+      if (runs.empty() || runs.back().phase != ph || runs.back().logn != logn)
+        runs.push_back({ph, logn, (int)items.size(), 0});
+      const int cnt = ph == 0 ? 3 * (int)probs[i].n - 1
+                      : ph == 3 ? (int)probs[i].n
+                                : L.ip[i].z.C;
+      for (int r = 0; r < cnt; ++r) items.push_back(make_int4(i, ph, r, 0));
+      runs.back().count += cnt;
+    }
+  }
   e = hipMemcpyAsync(base + L.off_inst, inst.data(), sizeof(BatchInst) * count,
                      hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
@@ -182,14 +186,27 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
     e = launch_batch(d_inst, d_items, L.nitems, head, head + 1, 4 * count, grid, g_spin_limit, st, s);
     return status_from_hip(e, "batch kernel");
   }
-  // one launch per pass, over the items of that pass of every instance
-  int start = 0;
-  for (int ph = 0; ph < 4 && e == hipSuccess; ++ph) {
-    int cnt = phase_count[ph];
-    e = launch_batch_phase(d_inst, d_items + start, cnt, st, s);
-    start += cnt;
+  // one launch per pass and transform size
+  for (const Run& r : runs) {
+    if (e != hipSuccess) break;
+    e = launch_batch_phase(r.phase, r.logn, d_inst, d_items + r.start, r.count, st, s);
   }
   return status_from_hip(e, "batch kernels");
+}
+
+int32_t hmv_batch_launches(const hmv_problem* probs, int32_t count) {
+  BatchLayout L;
+  if (!batch_layout(probs, count, &L)) return HMV_EINVAL;
+  std::vector<int> limb, index;
+  for (int i = 0; i < count; ++i) {
+    limb.push_back(L.ip[i].z.logM);
+    index.push_back(L.ip[i].z.logNt - 1);
+  }
+  std::sort(limb.begin(), limb.end());
+  std::sort(index.begin(), index.end());
+  const int nl = (int)(std::unique(limb.begin(), limb.end()) - limb.begin());
+  const int ni = (int)(std::unique(index.begin(), index.end()) - index.begin());
+  return 2 * nl + 2 * ni;
 }
 
 int hmv_debug_batch_spin_limit(int32_t spins) {

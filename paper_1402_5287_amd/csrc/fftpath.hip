@@ -599,7 +599,7 @@ __device__ __forceinline__ void batch_done(int* ctr) {
 }
 
 // forward row transform (the body of k_rows_fwd for one row)
-__device__ void b_row_fwd(const uint64_t* in, int W, int P, int w, int L, int gather_n, int logM,
+__device__ __forceinline__ void b_row_fwd(const uint64_t* in, int W, int P, int w, int L, int gather_n, int logM,
                           double2* out, int rows_alloc, int r, double2* buf, uint64_t* wd,
                           uint32_t* red, DevStatus* st) {
   const int T = blockDim.x, t = threadIdx.x;
@@ -618,7 +618,7 @@ __device__ void b_row_fwd(const uint64_t* in, int W, int P, int w, int L, int ga
 }
 
 // index-axis transform of one column of H1 (even / odd halves, LDS FFT)
-__device__ void b_col_plan(const double2* H1, int rows, int logNt, double scale, double2* Hh,
+__device__ __forceinline__ void b_col_plan(const double2* H1, int rows, int logNt, double scale, double2* Hh,
                            int c, double2* buf) {
   const int T = blockDim.x, t = threadIdx.x;
   const int logNh = logNt - 1, Nh = 1 << logNh;
@@ -626,10 +626,24 @@ __device__ void b_col_plan(const double2* H1, int rows, int logNt, double scale,
   const double2* col = H1 + tile_index(c, 0, rows);
   double2* he = Hh + (int64_t)c * (2 * Nh);
   for (int half = 0; half < 2; ++half) {
-    for (int s = t; s < Nh; s += T) {
-      const double2 lo = s < rows ? col[(int64_t)s * 8] : make_double2(0.0, 0.0);
-      const double2 hi = s + Nh < rows ? col[(int64_t)(s + Nh) * 8] : make_double2(0.0, 0.0);
-      buf[swz(s)] = half == 0 ? cadd(lo, hi) : cmul(csub(lo, hi), g_rtw[s * rs]);
+    // four elements per thread at a time, loads first (clamped addresses)
+    for (int s0 = t; s0 < Nh; s0 += 4 * T) {
+      double2 lo[4], hi[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = s0 + u * T;
+        lo[u] = col[(int64_t)(s < rows ? s : 0) * 8];
+        hi[u] = col[(int64_t)(s + Nh < rows ? s + Nh : 0) * 8];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = s0 + u * T;
+        if (s < Nh) {
+          const double2 l = s < rows ? lo[u] : make_double2(0.0, 0.0);
+          const double2 h = s + Nh < rows ? hi[u] : make_double2(0.0, 0.0);
+          buf[swz(s)] = half == 0 ? cadd(l, h) : cmul(csub(l, h), g_rtw[s * rs]);
+        }
+      }
     }
     __syncthreads();
     fft_lds(buf, logNh, -1);
@@ -644,7 +658,7 @@ __device__ void b_col_plan(const double2* H1, int rows, int logNt, double scale,
 
 // index-axis pass of one column: even half in buf[0, Nh), odd half in
 // buf[Nh, 2 Nh)
-__device__ void b_col_pass(const double2* X1, const double2* Hh, int n, int logNt, double2* Y1,
+__device__ __forceinline__ void b_col_pass(const double2* X1, const double2* Hh, int n, int logNt, double2* Y1,
                            int c, double2* buf) {
   const int T = blockDim.x, t = threadIdx.x;
   const int logNh = logNt - 1, Nh = 1 << logNh;
@@ -653,17 +667,42 @@ __device__ void b_col_pass(const double2* X1, const double2* Hh, int n, int logN
   const double2* he = Hh + (int64_t)c * (2 * Nh);
   double2* be = buf;
   double2* bo = buf + Nh;
-  for (int s = t; s < Nh; s += T) {
-    const double2 xv = s < n ? xcol[(int64_t)(n - 1 - s) * 8] : make_double2(0.0, 0.0);
-    be[swz(s)] = xv;
-    bo[swz(s)] = cmul(xv, g_rtw[s * rs]);
+  for (int s0 = t; s0 < Nh; s0 += 4 * T) {
+    double2 xv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int s = s0 + u * T;
+      xv[u] = xcol[(int64_t)(s < n ? n - 1 - s : 0) * 8];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int s = s0 + u * T;
+      if (s < Nh) {
+        const double2 v = s < n ? xv[u] : make_double2(0.0, 0.0);
+        be[swz(s)] = v;
+        bo[swz(s)] = cmul(v, g_rtw[s * rs]);
+      }
+    }
   }
   __syncthreads();
   fft_lds(be, logNh, -1);
   fft_lds(bo, logNh, -1);
-  for (int f = t; f < Nh; f += T) {
-    be[swz(f)] = cmul(be[swz(f)], he[f]);
-    bo[swz(f)] = cmul(bo[swz(f)], he[Nh + f]);
+  for (int f0 = t; f0 < Nh; f0 += 4 * T) {
+    double2 he4[4], ho4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = f0 + u * T < Nh ? f0 + u * T : 0;
+      he4[u] = he[f];
+      ho4[u] = he[Nh + f];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int f = f0 + u * T;
+      if (f < Nh) {
+        be[swz(f)] = cmul(be[swz(f)], he4[u]);
+        bo[swz(f)] = cmul(bo[swz(f)], ho4[u]);
+      }
+    }
   }
   __syncthreads();
   fft_lds(be, logNh, +1);
@@ -680,7 +719,7 @@ __device__ void b_col_pass(const double2* X1, const double2* Hh, int n, int logN
 }
 
 // inverse row transform, rounding and carry of one output row
-__device__ void b_row_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
+__device__ __forceinline__ void b_row_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
                           int out_reverse, uint64_t* y, int i, double2* buf, uint32_t* red,
                           DevStatus* st) {
   __shared__ RowStatus rst;
@@ -799,12 +838,14 @@ __global__ void __launch_bounds__(256) k_batch(const BatchInst* __restrict__ ins
   }
 }
 
-// Phase-synchronous batch: one launch per pass over the items of that pass
-// of every instance (one item per work-group); kernel boundaries order the
-// passes, so no work-group waits on another.
-__global__ void __launch_bounds__(256) k_batch_phase(const BatchInst* __restrict__ inst,
-                                                     const int4* __restrict__ items, int nitems,
-                                                     DevStatus* st) {
+// Phase-synchronous batch: one launch per pass and transform size, over the
+// items of that pass of every instance (one item per work-group); kernel
+// boundaries order the passes, so no work-group waits on another.  Each pass
+// has its own kernel, so each gets the registers it needs, and each launch
+// gets the LDS and the threads of its transform size.
+__global__ void __launch_bounds__(256, 2) k_batch_rows_fwd(const BatchInst* __restrict__ inst,
+                                                        const int4* __restrict__ items,
+                                                        int nitems, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint64_t wd[kMaxWords];
   __shared__ uint32_t red[32];
@@ -813,29 +854,72 @@ __global__ void __launch_bounds__(256) k_batch_phase(const BatchInst* __restrict
   const int4 d = items[it];
   const BatchInst I = inst[d.x];
   const int rows_h = 2 * I.n - 1;
-  if (d.y == 0) {
-    if (d.z < rows_h)
-      b_row_fwd(I.h, I.W, I.P, I.w, I.L, I.gather, I.logM, I.H1, rows_h, d.z, buf, wd, red, st);
-    else
-      b_row_fwd(I.x, I.W, I.P, I.w, I.L, 0, I.logM, I.X1, I.n, d.z - rows_h, buf, wd, red, st);
-  } else if (d.y == 1) {
-    b_col_plan(I.H1, rows_h, I.logNt, I.scale, I.Hh, d.z, buf);
-  } else if (d.y == 2) {
-    b_col_pass(I.X1, I.Hh, I.n, I.logNt, I.Y1, d.z, buf);
-  } else {
-    b_row_inv(I.Y1, I.n, I.logM, I.L, I.w, I.P, I.W, I.reverse, I.y, d.z, buf, red, st);
-  }
+  if (d.z < rows_h)
+    b_row_fwd(I.h, I.W, I.P, I.w, I.L, I.gather, I.logM, I.H1, rows_h, d.z, buf, wd, red, st);
+  else
+    b_row_fwd(I.x, I.W, I.P, I.w, I.L, 0, I.logM, I.X1, I.n, d.z - rows_h, buf, wd, red, st);
 }
 
-hipError_t launch_batch_phase(const BatchInst* inst, const int4* items, int nitems, DevStatus* st,
-                              hipStream_t s) {
+__global__ void __launch_bounds__(256, 2) k_batch_cols_plan(const BatchInst* __restrict__ inst,
+                                                         const int4* __restrict__ items,
+                                                         int nitems, DevStatus*) {
+  extern __shared__ double2 buf[];
+  const int it = blockIdx.x;
+  if (it >= nitems) return;
+  const int4 d = items[it];
+  const BatchInst I = inst[d.x];
+  b_col_plan(I.H1, 2 * I.n - 1, I.logNt, I.scale, I.Hh, d.z, buf);
+}
+
+__global__ void __launch_bounds__(256, 2) k_batch_cols_pass(const BatchInst* __restrict__ inst,
+                                                         const int4* __restrict__ items,
+                                                         int nitems, DevStatus*) {
+  extern __shared__ double2 buf[];
+  const int it = blockIdx.x;
+  if (it >= nitems) return;
+  const int4 d = items[it];
+  const BatchInst I = inst[d.x];
+  b_col_pass(I.X1, I.Hh, I.n, I.logNt, I.Y1, d.z, buf);
+}
+
+__global__ void __launch_bounds__(256, 2) k_batch_rows_inv(const BatchInst* __restrict__ inst,
+                                                        const int4* __restrict__ items,
+                                                        int nitems, DevStatus* st) {
+  extern __shared__ double2 buf[];
+  __shared__ uint32_t red[32];
+  const int it = blockIdx.x;
+  if (it >= nitems) return;
+  const int4 d = items[it];
+  const BatchInst I = inst[d.x];
+  b_row_inv(I.Y1, I.n, I.logM, I.L, I.w, I.P, I.W, I.reverse, I.y, d.z, buf, red, st);
+}
+
+// Items of one pass whose transforms have 2^logn points (the limb transform
+// for passes 0 and 3, the index-axis half for passes 1 and 2).
+hipError_t launch_batch_phase(int phase, int logn, const BatchInst* inst, const int4* items,
+                              int nitems, DevStatus* st, hipStream_t s) {
   if (nitems <= 0) return hipSuccess;
   hipError_t e = fft_tables_init();
   if (e != hipSuccess) return e;
-  const size_t lds = kBatchDynLds;
-  e = set_lds((const void*)k_batch_phase, lds);
+  const int N = 1 << logn;
+  const int T = fft_threads(N, 16);
+  const void* fn = phase == 0   ? (const void*)k_batch_rows_fwd
+                   : phase == 1 ? (const void*)k_batch_cols_plan
+                   : phase == 2 ? (const void*)k_batch_cols_pass
+                                : (const void*)k_batch_rows_inv;
+  size_t lds = sizeof(double2) * (size_t)N;
+  if (phase == 2) lds *= 2;                                  // both halves
+  if (phase == 3) lds += (size_t)carry_lds_bytes(T) + 16;   // coefficients + carry scratch
+  e = set_lds(fn, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_phase, dim3(nitems), dim3(kBatchThreads), lds, s, inst, items, nitems, st);
+  if (phase == 0)
+    hipLaunchKernelGGL(k_batch_rows_fwd, dim3(nitems), dim3(T), lds, s, inst, items, nitems, st);
+  else if (phase == 1)
+    hipLaunchKernelGGL(k_batch_cols_plan, dim3(nitems), dim3(T), lds, s, inst, items, nitems, st);
+  else if (phase == 2)
+    hipLaunchKernelGGL(k_batch_cols_pass, dim3(nitems), dim3(T), lds, s, inst, items, nitems, st);
+  else
+    hipLaunchKernelGGL(k_batch_rows_inv, dim3(nitems), dim3(T), lds, s, inst, items, nitems, st);
   return hipGetLastError();
 }
 

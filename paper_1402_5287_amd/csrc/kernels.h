@@ -10,9 +10,9 @@ namespace hmv {
 struct DevStatus;
 
 constexpr int kMaxWords = 648;      // W for P up to 40960 is 641
-constexpr int kSchoolMaxK = 16;
-constexpr int kSchoolThreads = 512;   // work-group size of the schoolbook row kernel
-constexpr int kBatchThreads = 256;    // work-group size of the batch kernels     // coefficients per thread in the schoolbook row kernel
+constexpr int kSchoolMaxK = 16;      // coefficients per thread in the schoolbook row kernel
+constexpr int kSchoolThreads = 512;  // work-group size of the schoolbook row kernel
+constexpr int kBatchThreads = 256;   // work-group size of the single-launch batch kernel
 
 // status block
 hipError_t launch_clear_status(DevStatus* st, hipStream_t s);
@@ -90,7 +90,9 @@ struct BatchInst {
 constexpr size_t kBatchDynLds = 68 * 1024;   // dynamic LDS of the batch kernel
 hipError_t launch_batch(const BatchInst* inst, const int4* items, int nitems, int* head, int* ctr,
                         int nctr, int grid, int spin_limit, DevStatus* st, hipStream_t s);
-hipError_t launch_batch_phase(const BatchInst* inst, const int4* items, int nitems, DevStatus* st,
-                              hipStream_t s);
+// one pass (0 forward rows, 1 plan columns, 2 matvec columns, 3 inverse rows)
+// over items whose transforms have 2^logn points
+hipError_t launch_batch_phase(int phase, int logn, const BatchInst* inst, const int4* items,
+                              int nitems, DevStatus* st, hipStream_t s);
 
 }  // namespace hmv

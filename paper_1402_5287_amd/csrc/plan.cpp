@@ -112,8 +112,9 @@ hipError_t time_launches(F launch, int reps, hipEvent_t a, hipEvent_t b, hipStre
 
 // Times the variants with the row spectra of h (first n rows of the plan
 // scratch) as x's spectra; the outputs are discarded and the status block
-// is cleared afterwards.
-int fft_tune(hmv_plan* p, DevStatus* st, char* scratch, hipStream_t s) {
+// is cleared afterwards.  Without may_run (one-shot calls) a shape that has
+// not been tuned keeps the first variants.
+int fft_tune(hmv_plan* p, DevStatus* st, char* scratch, bool may_run, hipStream_t s) {
   const std::tuple<int, int64_t, int32_t, int> key{p->device, p->n, p->P, p->w};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -124,6 +125,7 @@ int fft_tune(hmv_plan* p, DevStatus* st, char* scratch, hipStream_t s) {
       return HMV_OK;
     }
   }
+  if (!may_run) return HMV_OK;
   const int n = (int)p->n, W = (int)words_of(p->P);
   double2* X1 = reinterpret_cast<double2*>(scratch + align_up(kNormSlots * 8));
   double2* Y1 = X1 + align_up(16 * 8 * int64_t(p->tiles) * n) / 16;
@@ -167,7 +169,7 @@ int fft_tune(hmv_plan* p, DevStatus* st, char* scratch, hipStream_t s) {
 
 int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
                    int64_t scratch_bytes, char* plan_mem, int64_t plan_bytes, int force_w,
-                   hipStream_t s) {
+                   bool may_tune, hipStream_t s) {
   const int64_t n = p->n;
   const int32_t P = p->P;
   const int W = (int)words_of(P);
@@ -247,7 +249,7 @@ int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
     p->rows_inv_variant = g_force_rinv >= 0 ? g_force_rinv : 0;
     return HMV_OK;
   }
-  if (g_autotune) return fft_tune(p, st, scratch, s);
+  if (g_autotune) return fft_tune(p, st, scratch, may_tune, s);
   return HMV_OK;
 }
 
@@ -612,7 +614,8 @@ int oneshot_planned(int kind, const uint64_t* h, const uint64_t* x, uint64_t* y,
   if (!ws || ws_bytes < align_up(wb) + pb) return HMV_ENOMEM;
   char* base = static_cast<char*>(ws);
   hmv_plan* p = nullptr;
-  int rc = hmv_plan_h(&p, kind, h, n, P, algo, base + align_up(wb), pb, base, wb, s);
+  // one-shot calls reuse tuned launch variants but run no tuning of their own
+  int rc = plan_h_impl(&p, kind, h, n, P, algo, base + align_up(wb), pb, base, wb, s, false);
   if (rc != HMV_OK) return rc;
   rc = hmv_plan_matvec(p, x, y, base, wb, s);
   hmv_plan_destroy(p);
@@ -639,6 +642,16 @@ int64_t hmv_workspace_bytes(int kind, int64_t n, int32_t P, int algo) {
 
 int hmv_plan_h(hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P, int algo,
                void* plan_mem, int64_t plan_bytes, void* ws, int64_t ws_bytes, void* stream) {
+  return plan_h_impl(out, kind, h, n, P, algo, plan_mem, plan_bytes, ws, ws_bytes, stream, true);
+}
+
+}  // extern "C"
+
+namespace hmv {
+
+int plan_h_impl(hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P, int algo,
+                void* plan_mem, int64_t plan_bytes, void* ws, int64_t ws_bytes, void* stream,
+                bool may_tune) {
   if (!out || !h || !plan_mem || !ws) return HMV_EINVAL;
   if (!args_ok(kind, n, P)) return HMV_EINVAL;
   *out = nullptr;
@@ -669,7 +682,7 @@ int hmv_plan_h(hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P
   char* pm = static_cast<char*>(plan_mem);
   if (a == HMV_SPLIT_FFT || a == HMV_AUTO) {
     p->algo = HMV_SPLIT_FFT;
-    rc = fft_plan_build(p, h, st, scratch, scratch_bytes, pm, plan_bytes, g_force_w, s);
+    rc = fft_plan_build(p, h, st, scratch, scratch_bytes, pm, plan_bytes, g_force_w, may_tune, s);
     if (a == HMV_AUTO && (rc == HMV_EBOUND || rc == HMV_EUNSUPPORTED)) {
       // no binary64 width passes the bound: fall back to the exact NTT path
       p->algo = HMV_NTT;
@@ -689,6 +702,10 @@ int hmv_plan_h(hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P
   *out = p;
   return HMV_OK;
 }
+
+}  // namespace hmv
+
+extern "C" {
 
 int hmv_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, void* ws, int64_t ws_bytes,
                     void* stream) {

@@ -5,6 +5,8 @@
 
 #include <vector>
 
+#include "hmv.h"
+
 namespace hmv {
 
 constexpr int64_t kAlign = 256;
@@ -61,6 +63,11 @@ bool fft_worst_sizes(int64_t n, int32_t P, FftSizes* z);
 
 // planned paths (split-FFT, NTT, Karatsuba) used by the one-shot entry points
 int64_t oneshot_planned_bytes(int kind, int64_t n, int32_t P, int algo);
+// hmv_plan_h with control over the launch tuning runs (one-shot calls pass
+// false: they use tuned variants only when the shape was tuned before)
+int plan_h_impl(::hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_t P, int algo,
+                void* plan_mem, int64_t plan_bytes, void* ws, int64_t ws_bytes, void* stream,
+                bool may_tune);
 int oneshot_planned(int kind, const uint64_t* h, const uint64_t* x, uint64_t* y, int64_t n,
                     int32_t P, int algo, void* ws, int64_t ws_bytes, hipStream_t s);
 

@@ -40,6 +40,7 @@ SIGNATURES = {
                             _vp, _c_i64, _vp]),
     "hmv_plan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp]),
     "hmv_debug_force_variants": (_c_int, [_c_i32, _c_i32]),
+    "hmv_batch_launches": (_c_i32, [_vp, _c_i32]),
     "hmv_autotune": (_c_int, [_c_i32]),
     "hmv_plan_workspace_bytes": (_c_i64, [_vp]),
     "hmv_plan_matvec_events": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp, ctypes.POINTER(_vp)]),
@@ -281,9 +282,16 @@ def batch_workspace_bytes(problems) -> int:
     return int(b)
 
 
+def batch_launches(problems) -> int:
+    n = lib().hmv_batch_launches(ctypes.cast(problems, ctypes.c_void_p), len(problems))
+    if n < 0:
+        raise HmvError(int(n), "hmv_batch_launches")
+    return int(n)
+
+
 def batch_matvec(problems, ws, stream=None, check=True) -> int:
-    """All products of `problems` (from batch_problems): one launch per pass,
-    each launch covering every instance (four launches)."""
+    """All products of `problems` (from batch_problems): one launch per pass
+    and transform size, each covering every instance of that size."""
     rc = lib().hmv_batch_matvec(ctypes.cast(problems, ctypes.c_void_p), len(problems), _ptr(ws),
                                 ws.numel(), _stream(stream))
     if check:
