@@ -168,13 +168,19 @@ __device__ inline uint32_t raw_digit(const uint64_t* wd, int W, uint64_t signw, 
   return (uint32_t)(v & ((1ull << w) - 1ull));
 }
 
+// Digits a thread keeps in registers while splitting (chunks of at most this
+// many digits; longer chunks read their fields from LDS twice).
+constexpr int kSplitRegs = 16;
+
 // Balanced digits of the number in `wd` (LDS, W words).  Threads own
 // contiguous chunks of ceil(L / blockDim) digits; store(e, d) is called once
 // per digit.  The balancing carry c_{e+1} = [u_e + c_e >= 2^(w-1)] is resolved
 // with a block scan of generate / propagate / kill codes.  `lds` = 32 slots.
+// A chunk of at most kSplitRegs digits is read once, as one stream of bits
+// through a 128-bit window (one LDS word per 64 bits), and kept in registers.
 template <class Store>
 __device__ __forceinline__ void split_balanced(const uint64_t* wd, int W, int w, int L, Store store,
-                                      uint32_t* lds) {
+                                               uint32_t* lds) {
   const uint64_t signw = (wd[W - 1] >> 63) ? ~0ull : 0ull;
   const int per = (L + blockDim.x - 1) / blockDim.x;
   const int e0 = threadIdx.x * per;
@@ -182,6 +188,48 @@ __device__ __forceinline__ void split_balanced(const uint64_t* wd, int W, int w,
   const uint32_t half = 1u << (w - 1);
   BalOp op;
   uint32_t f = 2u;
+  if (per <= kSplitRegs) {                       // uniform
+    const int cnt = e1 > e0 ? e1 - e0 : 0;
+    const uint32_t mask = (1u << w) - 1u;
+    uint32_t u[kSplitRegs];
+    const int bit = e0 * w;
+    int q = bit >> 6;
+    unsigned __int128 acc = 0;
+    int avail = 0;
+    if (cnt > 0) {
+      acc = (unsigned __int128)((q < W ? wd[q] : signw) >> (bit & 63));
+      avail = 64 - (bit & 63);
+      ++q;
+    }
+#pragma unroll
+    for (int j = 0; j < kSplitRegs; ++j) {
+      u[j] = 0u;
+      if (j < cnt) {
+        if (avail < w) {
+          acc |= (unsigned __int128)(q < W ? wd[q] : signw) << avail;
+          avail += 64;
+          ++q;
+        }
+        u[j] = (uint32_t)acc & mask;
+        acc >>= w;
+        avail -= w;
+        const uint32_t g = u[j] >= half ? 1u : (u[j] == half - 1u ? 2u : 0u);
+        f = op(f, g);
+      }
+    }
+    const uint32_t cin = block_exclusive_scan(f, 2u, op, lds);
+    int c = (cin == 1u) ? 1 : 0;
+#pragma unroll
+    for (int j = 0; j < kSplitRegs; ++j) {
+      if (j < cnt) {
+        const int sv = (int)u[j] + c;
+        const bool hi = sv >= (int)half;
+        store(e0 + j, hi ? sv - (1 << w) : sv);
+        c = hi ? 1 : 0;
+      }
+    }
+    return;
+  }
   for (int e = e0; e < e1; ++e) {
     const uint32_t u = raw_digit(wd, W, signw, w, e);
     const uint32_t g = u >= half ? 1u : (u == half - 1u ? 2u : 0u);

@@ -164,9 +164,12 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   load_words(in + (int64_t)src * W, W, wd);
   __syncthreads();
   if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
-  // digit e is the real (e even) or imaginary (e odd) part of element e/2
+  // digit e is the real (e even) or imaginary (e odd) part of element e/2;
+  // the elements past the digits are zero (and the imaginary half of the
+  // last one when L is odd)
   double* bd = reinterpret_cast<double*>(buf);
-  for (int e = L + t; e < 2 * M; e += T) bd[2 * swz(e >> 1) + (e & 1)] = 0.0;
+  for (int k = (L + 1) / 2 + t; k < M; k += T) buf[swz(k)] = make_double2(0.0, 0.0);
+  if ((L & 1) && t == 0) bd[2 * swz(L >> 1) + 1] = 0.0;
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * swz(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);
@@ -609,7 +612,8 @@ __device__ __forceinline__ void b_row_fwd(const uint64_t* in, int W, int P, int 
   __syncthreads();
   if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
   double* bd = reinterpret_cast<double*>(buf);
-  for (int e = L + t; e < 2 * M; e += T) bd[2 * swz(e >> 1) + (e & 1)] = 0.0;
+  for (int k = (L + 1) / 2 + t; k < M; k += T) buf[swz(k)] = make_double2(0.0, 0.0);
+  if ((L & 1) && t == 0) bd[2 * swz(L >> 1) + 1] = 0.0;
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * swz(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);
