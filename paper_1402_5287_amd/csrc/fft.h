@@ -129,10 +129,16 @@ __device__ __forceinline__ void dft<16>(double2* v, int sign) {
   }
 }
 
-// LDS slot of element i: the low 4 index bits are XOR-ed with the next 4.
-// A bijection inside every aligned block of 256 (and of N when N < 256); it
-// spreads the stride-16 accesses of the early passes over all banks.
-__device__ __forceinline__ int swz(int i) { return i ^ ((i >> 4) & 15); }
+// LDS slot of element i: one spare slot after every 16 elements.  Strided
+// accesses (stride 16 and 256 points) then fall on distinct bank groups,
+// and every per-element offset inside a pass is a constant that the LDS
+// instructions take as an immediate.  An N-point buffer needs
+// lds_points(N) slots.
+__device__ __forceinline__ int lds_slot(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_points(int N) { return N + (N >> 4); }
+// lds_slot(i + r * s) for a stride s that is a multiple of 16, given
+// si = lds_slot(i): the slot step per r is the constant s + s/16
+__device__ __forceinline__ int lds_step(int si, int r, int s) { return si + r * (s + (s >> 4)); }
 
 // One Stockham pass over N points held in buf (LDS).  Requires
 // blockDim.x * NB >= N / R.  Ends with a barrier.
@@ -148,7 +154,8 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int N, int Ns, int s
     if (b < nbf) {
       const int k = b & (Ns - 1);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[swz(b + r * nbf)];
+      for (int r = 0; r < R; ++r)
+        v[i][r] = buf[(nbf & 15) == 0 ? lds_step(lds_slot(b), r, nbf) : lds_slot(b + r * nbf)];
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -168,14 +175,15 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int N, int Ns, int s
       dft<R>(v[i], sign);
       const int base = (b - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[swz(base + r * Ns)] = v[i][r];
+      for (int r = 0; r < R; ++r)
+        buf[(Ns & 15) == 0 ? lds_step(lds_slot(base), r, Ns) : lds_slot(base + r * Ns)] = v[i][r];
     }
   }
   __syncthreads();
 }
 
 // Full transform of N = 2^logN points (2 <= N <= 8192) in buf (element i in
-// slot swz(i)).  Requires
+// slot lds_slot(i)).  Requires
 // blockDim.x >= N / 16 (blockDim.x >= 1 for N < 16).  Caller must have
 // synchronised after filling buf; ends with a barrier.
 __device__ __forceinline__ void fft_lds(double2* buf, int logN, int sign) {
@@ -211,7 +219,8 @@ __device__ __forceinline__ void last_pass_to_regs(const double2* buf, int N, int
     const int b = t + i * Ta;      // butterfly index; k = b since b < Ns
     double2 u[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) u[r] = buf[swz(b + r * Ns)];
+    for (int r = 0; r < R; ++r)
+      u[r] = buf[(Ns & 15) == 0 ? lds_step(lds_slot(b), r, Ns) : lds_slot(b + r * Ns)];
 #pragma unroll
     for (int r = 1; r < R; ++r) {
       double2 w = tw[b * (R - 1) + (r - 1)];
@@ -238,7 +247,7 @@ __device__ __forceinline__ void fft_regs(double2* v, double2* buf, int sign) {
     if (act) {
       dft<16>(v, sign);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) buf[swz(16 * t + r)] = v[r];
+      for (int r = 0; r < 16; ++r) buf[17 * t + r] = v[r];     // lds_slot(16 t + r)
     }
     __syncthreads();
     constexpr int NMID = (REM ? A : A - 1) - 1;
@@ -266,7 +275,7 @@ __device__ __forceinline__ void fft_regs8(double2* v, double2* buf, int sign) {
   if (act) {
     dft<8>(v, sign);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) buf[swz(8 * t + r)] = v[r];
+    for (int r = 0; r < 8; ++r) buf[8 * t + (t >> 1) + r] = v[r];   // lds_slot(8 t + r)
   }
   __syncthreads();
   constexpr int NMID = LOGN / 3 - 2;
@@ -281,7 +290,8 @@ __device__ __forceinline__ void fft_regs8(double2* v, double2* buf, int sign) {
     const double2* tw = g_tw + tw_offset(8, Ta);
     double2 u[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) u[r] = buf[swz(t + r * Ta)];
+    for (int r = 0; r < 8; ++r)
+      u[r] = buf[(Ta & 15) == 0 ? lds_step(lds_slot(t), r, Ta) : lds_slot(t + r * Ta)];
 #pragma unroll
     for (int r = 1; r < 8; ++r) {
       double2 w = tw[t * 7 + (r - 1)];

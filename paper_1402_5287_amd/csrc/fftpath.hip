@@ -138,7 +138,7 @@ __device__ inline void pack_real_row(const double2* buf, int M, double2* __restr
     for (int u = 0; u < 8; ++u) {
       const int k = k0 + u * T;
       if (k <= M) {
-        const double2 zk = buf[swz(k & (M - 1))], zm = buf[swz((M - k) & (M - 1))];
+        const double2 zk = buf[lds_slot(k & (M - 1))], zm = buf[lds_slot((M - k) & (M - 1))];
         const double2 A = cadd(zk, conj2(zm)), B = csub(zk, conj2(zm));
         const double2 Q = cmul(wv[u], B);
         out[tile_index(k, r, rows_alloc)] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
@@ -168,9 +168,9 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   // the elements past the digits are zero (and the imaginary half of the
   // last one when L is odd)
   double* bd = reinterpret_cast<double*>(buf);
-  for (int k = (L + 1) / 2 + t; k < M; k += T) buf[swz(k)] = make_double2(0.0, 0.0);
-  if ((L & 1) && t == 0) bd[2 * swz(L >> 1) + 1] = 0.0;
-  split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * swz(e >> 1) + (e & 1)] = (double)d; }, red);
+  for (int k = (L + 1) / 2 + t; k < M; k += T) buf[lds_slot(k)] = make_double2(0.0, 0.0);
+  if ((L & 1) && t == 0) bd[2 * lds_slot(L >> 1) + 1] = 0.0;
+  split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);
   pack_real_row(buf, M, out, r, rows_alloc);
@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
       wk[j] = conj2(g_rtw[k * rs]);
     }
 #pragma unroll
-    for (int j = 0; j < per; ++j) buf[swz(t + Ta * j)] = v[j];
+    for (int j = 0; j < per; ++j) buf[lds_slot(t + Ta * j)] = v[j];
   }
   if (t == 0) ytop = top;
   __syncthreads();
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
     for (int j = 0; j < per; ++j) {
       const int k = t + Ta * j;
       const double2 yk = v[j];
-      const double2 ym = k == 0 ? ytop : buf[swz(M - k)];
+      const double2 ym = k == 0 ? ytop : buf[lds_slot(M - k)];
       const double2 E = cadd(yk, conj2(ym)), D = csub(yk, conj2(ym));
       const double2 Q = cmul(D, wk[j]);
       v[j] = make_double2(E.x - Q.y, E.y + Q.x);
@@ -430,7 +430,7 @@ hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int c
                            hipStream_t s) {
   const int M = 1 << logM;
   const int T = fft_threads(M, 16);           // the LDS transform needs N/16 threads
-  const size_t lds = sizeof(double2) * (size_t)M;
+  const size_t lds = sizeof(double2) * (size_t)lds_points(M);
   hipError_t e = set_lds((const void*)k_rows_fwd, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rows_fwd, dim3(count), dim3(T), lds, s, in, W, P, w, L, count, gather_n,
@@ -441,7 +441,7 @@ hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int c
 template <int LOGNH>
 hipError_t cols_plan_t(const double2* H1, int rows, int C, double scale, double2* Hh,
                        hipStream_t s) {
-  const size_t lds = sizeof(double2) * (size_t)(1 << LOGNH);
+  const size_t lds = sizeof(double2) * (size_t)lds_points(1 << LOGNH);
   hipError_t e = set_lds((const void*)k_cols_plan<LOGNH>, lds);
   if (e != hipSuccess) return e;
   const int grid = (C + 7) / 8 * 8;
@@ -453,7 +453,7 @@ hipError_t cols_plan_t(const double2* H1, int rows, int C, double scale, double2
 template <int LOGNH, int R>
 hipError_t cols_pass_r(const double2* X1, const double2* Hh, int n, int C, int linear,
                        double2* Y1, hipStream_t s) {
-  const size_t lds = sizeof(double2) * (size_t)(1 << LOGNH);
+  const size_t lds = sizeof(double2) * (size_t)lds_points(1 << LOGNH);
   hipError_t e = set_lds((const void*)k_cols_pass<LOGNH, R>, lds);
   if (e != hipSuccess) return e;
   const int grid = (C + 7) / 8 * 8;
@@ -510,7 +510,7 @@ hipError_t rows_inv_r(const double2* Y1, int n, int L, int w, int P, int W, int 
   const int NC = 2 * L - 1;
   // FFT points during the transform; afterwards NC int64 coefficients then
   // the carry scratch
-  const size_t fft_part = sizeof(double2) * (size_t)M;
+  const size_t fft_part = sizeof(double2) * (size_t)lds_points(M);
   const size_t carry_off = ((size_t)NC * 8 + 15) / 16 * 16;
   const size_t carry_part = carry_off + (size_t)carry_lds_bytes(T);
   const size_t lds = fft_part > carry_part ? fft_part : carry_part;
@@ -612,9 +612,9 @@ __device__ __forceinline__ void b_row_fwd(const uint64_t* in, int W, int P, int 
   __syncthreads();
   if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
   double* bd = reinterpret_cast<double*>(buf);
-  for (int k = (L + 1) / 2 + t; k < M; k += T) buf[swz(k)] = make_double2(0.0, 0.0);
-  if ((L & 1) && t == 0) bd[2 * swz(L >> 1) + 1] = 0.0;
-  split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * swz(e >> 1) + (e & 1)] = (double)d; }, red);
+  for (int k = (L + 1) / 2 + t; k < M; k += T) buf[lds_slot(k)] = make_double2(0.0, 0.0);
+  if ((L & 1) && t == 0) bd[2 * lds_slot(L >> 1) + 1] = 0.0;
+  split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);
   pack_real_row(buf, M, out, r, rows_alloc);
@@ -645,7 +645,7 @@ __device__ __forceinline__ void b_col_plan(const double2* H1, int rows, int logN
         if (s < Nh) {
           const double2 l = s < rows ? lo[u] : make_double2(0.0, 0.0);
           const double2 h = s + Nh < rows ? hi[u] : make_double2(0.0, 0.0);
-          buf[swz(s)] = half == 0 ? cadd(l, h) : cmul(csub(l, h), g_rtw[s * rs]);
+          buf[lds_slot(s)] = half == 0 ? cadd(l, h) : cmul(csub(l, h), g_rtw[s * rs]);
         }
       }
     }
@@ -653,15 +653,15 @@ __device__ __forceinline__ void b_col_plan(const double2* H1, int rows, int logN
     fft_lds(buf, logNh, -1);
     double2* dst = he + half * Nh;
     for (int f = t; f < Nh; f += T) {
-      const double2 v = buf[swz(f)];
+      const double2 v = buf[lds_slot(f)];
       dst[f] = make_double2(v.x * scale, v.y * scale);
     }
     __syncthreads();
   }
 }
 
-// index-axis pass of one column: even half in buf[0, Nh), odd half in
-// buf[Nh, 2 Nh)
+// index-axis pass of one column: even half in the first lds_points(Nh)
+// slots of buf, odd half in the next
 __device__ __forceinline__ void b_col_pass(const double2* X1, const double2* Hh, int n, int logNt, double2* Y1,
                            int c, double2* buf) {
   const int T = blockDim.x, t = threadIdx.x;
@@ -670,7 +670,7 @@ __device__ __forceinline__ void b_col_pass(const double2* X1, const double2* Hh,
   const double2* xcol = X1 + tile_index(c, 0, n);
   const double2* he = Hh + (int64_t)c * (2 * Nh);
   double2* be = buf;
-  double2* bo = buf + Nh;
+  double2* bo = buf + lds_points(Nh);
   for (int s0 = t; s0 < Nh; s0 += 4 * T) {
     double2 xv[4];
 #pragma unroll
@@ -683,8 +683,8 @@ __device__ __forceinline__ void b_col_pass(const double2* X1, const double2* Hh,
       const int s = s0 + u * T;
       if (s < Nh) {
         const double2 v = s < n ? xv[u] : make_double2(0.0, 0.0);
-        be[swz(s)] = v;
-        bo[swz(s)] = cmul(v, g_rtw[s * rs]);
+        be[lds_slot(s)] = v;
+        bo[lds_slot(s)] = cmul(v, g_rtw[s * rs]);
       }
     }
   }
@@ -703,8 +703,8 @@ __device__ __forceinline__ void b_col_pass(const double2* X1, const double2* Hh,
     for (int u = 0; u < 4; ++u) {
       const int f = f0 + u * T;
       if (f < Nh) {
-        be[swz(f)] = cmul(be[swz(f)], he4[u]);
-        bo[swz(f)] = cmul(bo[swz(f)], ho4[u]);
+        be[lds_slot(f)] = cmul(be[lds_slot(f)], he4[u]);
+        bo[lds_slot(f)] = cmul(bo[lds_slot(f)], ho4[u]);
       }
     }
   }
@@ -713,8 +713,8 @@ __device__ __forceinline__ void b_col_pass(const double2* X1, const double2* Hh,
   fft_lds(bo, logNh, +1);
   double2* ycol = Y1 + tile_index(c, 0, n);
   for (int s = t; s < Nh; s += T) {
-    const double2 e = be[swz(s)];
-    const double2 q = cmul(bo[swz(s)], conj2(g_rtw[s * rs]));
+    const double2 e = be[lds_slot(s)];
+    const double2 q = cmul(bo[lds_slot(s)], conj2(g_rtw[s * rs]));
     const int ra = s - (n - 1), rb = s + Nh - (n - 1);
     if (ra >= 0 && ra < n) ycol[(int64_t)ra * 8] = cadd(e, q);
     if (rb >= 0 && rb < n) ycol[(int64_t)rb * 8] = csub(e, q);
@@ -743,7 +743,7 @@ __device__ __forceinline__ void b_row_inv(const double2* Y1, int n, int logM, in
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int k = k0 + u * T;
-      if (k < M) buf[swz(k)] = ld[u];
+      if (k < M) buf[lds_slot(k)] = ld[u];
     }
   }
   if (t == 0) ytop = Y1[tile_index(M, i, n)];
@@ -753,8 +753,8 @@ __device__ __forceinline__ void b_row_inv(const double2* Y1, int n, int logM, in
   for (int a = 0; a < 16; ++a) {
     const int k = t + a * T;
     if (k < M) {
-      const double2 yk = buf[swz(k)];
-      const double2 ym = k == 0 ? ytop : buf[swz(M - k)];
+      const double2 yk = buf[lds_slot(k)];
+      const double2 ym = k == 0 ? ytop : buf[lds_slot(M - k)];
       const double2 E = cadd(yk, conj2(ym)), D = csub(yk, conj2(ym));
       const double2 Q = cmul(D, conj2(g_rtw[k * rs]));
       z[a] = make_double2(E.x - Q.y, E.y + Q.x);
@@ -764,7 +764,7 @@ __device__ __forceinline__ void b_row_inv(const double2* Y1, int n, int logM, in
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
     const int k = t + a * T;
-    if (k < M) buf[swz(k)] = z[a];
+    if (k < M) buf[lds_slot(k)] = z[a];
   }
   __syncthreads();
   fft_lds(buf, logM, +1);
@@ -775,7 +775,7 @@ __device__ __forceinline__ void b_row_inv(const double2* Y1, int n, int logM, in
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
     const int m = t + a * T;
-    if (m < M) v[a] = buf[swz(m)];
+    if (m < M) v[a] = buf[lds_slot(m)];
   }
   __syncthreads();
   int64_t* coef = reinterpret_cast<int64_t*>(buf);
@@ -911,7 +911,7 @@ hipError_t launch_batch_phase(int phase, int logn, const BatchInst* inst, const 
                    : phase == 1 ? (const void*)k_batch_cols_plan
                    : phase == 2 ? (const void*)k_batch_cols_pass
                                 : (const void*)k_batch_rows_inv;
-  size_t lds = sizeof(double2) * (size_t)N;
+  size_t lds = sizeof(double2) * (size_t)lds_points(N);
   if (phase == 2) lds *= 2;                                  // both halves
   if (phase == 3) lds += (size_t)carry_lds_bytes(T) + 16;   // coefficients + carry scratch
   e = set_lds(fn, lds);

@@ -87,7 +87,7 @@ struct BatchInst {
   double scale;
 };
 
-constexpr size_t kBatchDynLds = 68 * 1024;   // dynamic LDS of the batch kernel
+constexpr size_t kBatchDynLds = 72 * 1024;   // dynamic LDS of the batch kernel
 hipError_t launch_batch(const BatchInst* inst, const int4* items, int nitems, int* head, int* ctr,
                         int nctr, int grid, int spin_limit, DevStatus* st, hipStream_t s);
 // one pass (0 forward rows, 1 plan columns, 2 matvec columns, 3 inverse rows)
