@@ -199,6 +199,22 @@ __device__ __forceinline__ void fft_lds(double2* buf, int logN, int sign) {
   else if (rem == 3) stockham_pass<8, 2>(buf, N, Ns, sign);
 }
 
+// fft_lds with the size known at compile time (every pass's span, table
+// offset and slot steps become constants).
+template <int LOGN>
+__device__ __forceinline__ void fft_lds_t(double2* buf, int sign) {
+  constexpr int N = 1 << LOGN, A = LOGN >> 2, REM = LOGN & 3;
+  int Ns = 1;
+#pragma unroll
+  for (int p = 0; p < A; ++p) {
+    stockham_pass<16, 1>(buf, N, Ns, sign);
+    Ns <<= 4;
+  }
+  if constexpr (REM == 1) stockham_pass<2, 8>(buf, N, Ns, sign);
+  else if constexpr (REM == 2) stockham_pass<4, 4>(buf, N, Ns, sign);
+  else if constexpr (REM == 3) stockham_pass<8, 2>(buf, N, Ns, sign);
+}
+
 // ------------------------------------------------------------------------
 // Register-resident variant.  For N >= 16 the Ta = N/16 active threads each
 // hold 16 elements, element t + Ta*j in v[j]; for N < 16 thread 0 holds all

@@ -149,17 +149,18 @@ __device__ inline void pack_real_row(const double2* buf, int M, double2* __restr
 
 // Row pass, forward: split one number into digits, real FFT over the limb
 // axis (N_z = 2M real points), write the M+1 non-redundant bins.
+template <int LOGM>
 __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict__ in, int W, int P,
                                                      int w, int L, int count, int gather_n,
-                                                     int logM, double2* __restrict__ out,
-                                                     int rows_alloc, DevStatus* st) {
+                                                     double2* __restrict__ out, int rows_alloc,
+                                                     DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint64_t wd[kMaxWords];
   __shared__ uint32_t red[32];
   const int r = blockIdx.x;
   if (r >= count) return;
   const int T = blockDim.x, t = threadIdx.x;
-  const int M = 1 << logM;
+  constexpr int M = 1 << LOGM;
   const int src = gather_row(r, gather_n);
   load_words(in + (int64_t)src * W, W, wd);
   __syncthreads();
@@ -172,7 +173,7 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   if ((L & 1) && t == 0) bd[2 * lds_slot(L >> 1) + 1] = 0.0;
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
-  fft_lds(buf, logM, -1);
+  fft_lds_t<LOGM>(buf, -1);
   pack_real_row(buf, M, out, r, rows_alloc);
 }
 
@@ -425,17 +426,30 @@ hipError_t launch_h_norms(const uint64_t* h, int W, int P, int rows, int gather_
   return hipGetLastError();
 }
 
+template <int LOGM>
+hipError_t rows_fwd_t(const uint64_t* in, int W, int P, int w, int L, int count, int gather_n,
+                      double2* out, int rows_alloc, DevStatus* st, hipStream_t s) {
+  constexpr int M = 1 << LOGM;
+  const int T = fft_threads(M, 16);           // the LDS transform needs N/16 threads
+  const size_t lds = sizeof(double2) * (size_t)lds_points(M);
+  hipError_t e = set_lds((const void*)k_rows_fwd<LOGM>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rows_fwd<LOGM>, dim3(count), dim3(T), lds, s, in, W, P, w, L, count,
+                     gather_n, out, rows_alloc, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int count,
                            int gather_n, int logM, double2* out, int rows_alloc, DevStatus* st,
                            hipStream_t s) {
-  const int M = 1 << logM;
-  const int T = fft_threads(M, 16);           // the LDS transform needs N/16 threads
-  const size_t lds = sizeof(double2) * (size_t)lds_points(M);
-  hipError_t e = set_lds((const void*)k_rows_fwd, lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rows_fwd, dim3(count), dim3(T), lds, s, in, W, P, w, L, count, gather_n,
-                     logM, out, rows_alloc, st);
-  return hipGetLastError();
+  switch (logM) {
+#define HMV_RF(k) \
+  case k: return rows_fwd_t<k>(in, W, P, w, L, count, gather_n, out, rows_alloc, st, s);
+    HMV_RF(1) HMV_RF(2) HMV_RF(3) HMV_RF(4) HMV_RF(5) HMV_RF(6) HMV_RF(7) HMV_RF(8) HMV_RF(9)
+    HMV_RF(10) HMV_RF(11) HMV_RF(12)
+#undef HMV_RF
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int LOGNH>
