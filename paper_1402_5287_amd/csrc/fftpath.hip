@@ -75,6 +75,21 @@ __device__ __forceinline__ int xcd_slot(int b, int grid) {
   return (b & 7) * q + (b >> 3);
 }
 
+// Spectra of rows are stored in tiles of TW bins: bin k of row `row` at
+// ((k / TW) rows + row) TW + k % TW.  The row passes touch TW contiguous
+// bins per row, the index-axis pass reads a bin column at stride TW.
+#ifndef HMV_X1_TILE
+#define HMV_X1_TILE 2
+#endif
+#ifndef HMV_Y1_TILE
+#define HMV_Y1_TILE 8
+#endif
+constexpr int kX1Tile = HMV_X1_TILE;   // spectra of x (and of h while planning)
+constexpr int kY1Tile = HMV_Y1_TILE;   // spectra of y
+template <int TW>
+__device__ __forceinline__ int64_t tidx(int k, int row, int rows) {
+  return ((int64_t)(k / TW) * rows + row) * TW + (k % TW);
+}
 __device__ __forceinline__ int64_t tile_index(int k, int row, int rows) {
   return ((int64_t)(k >> 3) * rows + row) * 8 + (k & 7);
 }
@@ -123,6 +138,8 @@ __global__ void __launch_bounds__(256) k_h_norms(const uint64_t* __restrict__ h,
 //   X[k] = 1/2 (Z[k] + conj Z[M-k]) - i/2 w^k (Z[k] - conj Z[M-k]),
 // stored to row r of the tiled spectrum.  A thread's root loads are issued
 // eight at a time so that they are in flight together.
+// Stored in tiles of TW bins (tidx).
+template <int TW>
 __device__ inline void pack_real_row(const double2* buf, int M, double2* __restrict__ out, int r,
                                      int rows_alloc) {
   const int T = blockDim.x, t = threadIdx.x;
@@ -141,7 +158,8 @@ __device__ inline void pack_real_row(const double2* buf, int M, double2* __restr
         const double2 zk = buf[lds_slot(k & (M - 1))], zm = buf[lds_slot((M - k) & (M - 1))];
         const double2 A = cadd(zk, conj2(zm)), B = csub(zk, conj2(zm));
         const double2 Q = cmul(wv[u], B);
-        out[tile_index(k, r, rows_alloc)] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
+        const int64_t o = tidx<TW>(k, r, rows_alloc);
+        out[o] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
       }
     }
   }
@@ -157,7 +175,9 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   extern __shared__ double2 buf[];
   __shared__ uint64_t wd[kMaxWords];
   __shared__ uint32_t red[32];
-  const int r = blockIdx.x;
+  // rows grouped per XCD: the rows that share the lines of a bin column are
+  // written through one L2
+  const int r = xcd_slot(blockIdx.x, gridDim.x);
   if (r >= count) return;
   const int T = blockDim.x, t = threadIdx.x;
   constexpr int M = 1 << LOGM;
@@ -174,7 +194,7 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds_t<LOGM>(buf, -1);
-  pack_real_row(buf, M, out, r, rows_alloc);
+  pack_real_row<kX1Tile>(buf, M, out, r, rows_alloc);
 }
 
 // The index-axis transforms of N_t = 2 Nh points are split by one radix-2
@@ -203,7 +223,7 @@ __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H
   constexpr int rs = kRealTwN >> logNt;
   const int t = threadIdx.x;
   const bool act = t < Ta;
-  const double2* col = H1 + tile_index(c, 0, rows);
+  const double2* col = H1 + tidx<kX1Tile>(c, 0, rows);   // bin column, stride kX1Tile
   double2* he = Hh + (int64_t)c * (2 * Nh);
   double2* ho = he + Nh;
   double2 v[16];
@@ -214,8 +234,8 @@ __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H
 #pragma unroll
       for (int j = 0; j < per; ++j) {
         const int s = t + Ta * j;
-        const double2 lo = col[(int64_t)(s < rows ? s : 0) * 8];
-        const double2 hi = col[(int64_t)(s + Nh < rows ? s + Nh : 0) * 8];
+        const double2 lo = col[(int64_t)(s < rows ? s : 0) * kX1Tile];
+        const double2 hi = col[(int64_t)(s + Nh < rows ? s + Nh : 0) * kX1Tile];
         const double2 l = s < rows ? lo : make_double2(0.0, 0.0);
         const double2 u = s + Nh < rows ? hi : make_double2(0.0, 0.0);
         v[j] = half == 0 ? cadd(l, u) : cmul(csub(l, u), g_rtw[s * rs]);
@@ -251,10 +271,10 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
   constexpr int rs = kRealTwN >> logNt;
   const int t = threadIdx.x;
   const bool act = t < Ta;
-  const double2* xcol = X1 + tile_index(c, 0, n);
+  const double2* xcol = X1 + tidx<kX1Tile>(c, 0, n);   // bin column of x, stride kX1Tile
   const double2* he = Hh + (int64_t)c * (2 * Nh);
   const double2* ho = he + Nh;
-  double2* ycol = Y1 + tile_index(c, 0, n);
+  double2* ycol = Y1 + tidx<kY1Tile>(c, 0, n);
   // Every per-element loop sits in one guarded block with in-bounds
   // (clamped) addresses, so its loads are issued together rather than one
   // round trip per element.  With R = 16 the column is read from HBM once:
@@ -265,7 +285,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
 #pragma unroll
     for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
-      const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * 8];
+      const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * kX1Tile];
       v[j] = s < n ? xv : make_double2(0.0, 0.0);
       if constexpr (R == 16) o[j] = v[j];
     }
@@ -283,7 +303,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
     for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
       if constexpr (R != 16) {
-        const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * 8];
+        const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * kX1Tile];
         o[j] = s < n ? xv : make_double2(0.0, 0.0);
       }
       o[j] = cmul(o[j], g_rtw[s * rs]);
@@ -302,8 +322,8 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
       const int s = t + Ta * j;
       const double2 q = cmul(o[j], conj2(g_rtw[s * rs]));
       const int ra = s - (n - 1), rb = s + Nh - (n - 1);
-      if (ra >= 0 && ra < n) ycol[(int64_t)ra * 8] = cadd(v[j], q);
-      if (rb >= 0 && rb < n) ycol[(int64_t)rb * 8] = csub(v[j], q);
+      if (ra >= 0 && ra < n) ycol[(int64_t)ra * kY1Tile] = cadd(v[j], q);
+      if (rb >= 0 && rb < n) ycol[(int64_t)rb * kY1Tile] = csub(v[j], q);
     }
   }
 }
@@ -334,12 +354,12 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
   // the row and the packing roots, all loads in flight together (one
   // guarded block; element k = t + Ta j covers every k < M)
   double2 wk[R], v[R];
-  const double2 top = Y1[tile_index(M, i, n)];
+  const double2 top = Y1[tidx<kY1Tile>(M, i, n)];
   if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) {
       const int k = t + Ta * j;
-      v[j] = Y1[tile_index(k, i, n)];
+      v[j] = Y1[tidx<kY1Tile>(k, i, n)];
       wk[j] = conj2(g_rtw[k * rs]);
     }
 #pragma unroll
@@ -434,7 +454,8 @@ hipError_t rows_fwd_t(const uint64_t* in, int W, int P, int w, int L, int count,
   const size_t lds = sizeof(double2) * (size_t)lds_points(M);
   hipError_t e = set_lds((const void*)k_rows_fwd<LOGM>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rows_fwd<LOGM>, dim3(count), dim3(T), lds, s, in, W, P, w, L, count,
+  const int grid = (count + 7) / 8 * 8;         // xcd_slot needs a multiple of 8
+  hipLaunchKernelGGL(k_rows_fwd<LOGM>, dim3(grid), dim3(T), lds, s, in, W, P, w, L, count,
                      gather_n, out, rows_alloc, st);
   return hipGetLastError();
 }
@@ -631,7 +652,7 @@ __device__ __forceinline__ void b_row_fwd(const uint64_t* in, int W, int P, int 
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);
-  pack_real_row(buf, M, out, r, rows_alloc);
+  pack_real_row<8>(buf, M, out, r, rows_alloc);
   __syncthreads();
 }
 
