@@ -53,6 +53,10 @@ hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int
 namespace hmv {
 
 // exact paths modulo 2^64 - 2^32 + 1 (NTT and Karatsuba)
+// Tiles of the NTT path's row spectra (log2 residues per tile): x's and h's
+// spectra in tiles of 4 (32 bytes per row, read as strided columns by the
+// index-axis pass), y's in tiles of 16 (full lines for the inverse row pass)
+constexpr int kNttXLogT = 2, kNttYLogT = 4;
 hipError_t ntt_tables_init();
 hipError_t launch_ntt_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int count,
                                int gather_n, int logN, uint64_t* out, int rows_alloc, int logT,

@@ -77,7 +77,9 @@ __global__ void __launch_bounds__(512) k_ntt_rows_fwd(const uint64_t* __restrict
   __shared__ uint64_t wd[kMaxWords];
   __shared__ uint32_t red[32];
   __shared__ uint64_t r16[16];
-  const int r = blockIdx.x;
+  // rows grouped per XCD, so that the rows sharing the lines of a tile
+  // column are written through one L2
+  const int r = n_xcd_slot(blockIdx.x, gridDim.x);
   if (r >= count) return;
   const int T = blockDim.x, t = threadIdx.x, N = 1 << logN;
   if (t < 16) r16[t] = g_nr16[t];
@@ -176,8 +178,8 @@ __global__ void __launch_bounds__(512) k_ntt_cols_plan(const uint64_t* __restric
 #pragma unroll
       for (int j = 0; j < per; ++j) {
         const int s = t + Ta * j;
-        const uint64_t l = H1[ntile(c, s < rows ? s : 0, rows, 4)];
-        const uint64_t u = H1[ntile(c, s + Nh < rows ? s + Nh : 0, rows, 4)];
+        const uint64_t l = H1[ntile(c, s < rows ? s : 0, rows, kNttXLogT)];
+        const uint64_t u = H1[ntile(c, s + Nh < rows ? s + Nh : 0, rows, kNttXLogT)];
         const uint64_t lo = s < rows ? l : 0, hi = s + Nh < rows ? u : 0;
         v[j] = half == 0 ? gl_add(lo, hi) : gl_mul(gl_sub(lo, hi), g_nsplit[s * ss]);
       }
@@ -218,7 +220,7 @@ __global__ void __launch_bounds__(512) k_ntt_cols_pass(const uint64_t* __restric
 #pragma unroll
     for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
-      const uint64_t xv = X1[ntile(c, s < n ? n - 1 - s : 0, n, 4)];
+      const uint64_t xv = X1[ntile(c, s < n ? n - 1 - s : 0, n, kNttXLogT)];
       v[j] = s < n ? xv : 0;
       o[j] = v[j];
     }
@@ -246,8 +248,8 @@ __global__ void __launch_bounds__(512) k_ntt_cols_pass(const uint64_t* __restric
       const int s = t + Ta * j;
       const uint64_t q = gl_mul(o[j], g_nsplit[kNttSplitEntries + s * ss]);
       const int ra = s - (n - 1), rb = s + Nh - (n - 1);
-      if (ra >= 0 && ra < n) Y1[ntile(c, ra, n, 4)] = gl_add(v[j], q);
-      if (rb >= 0 && rb < n) Y1[ntile(c, rb, n, 4)] = gl_sub(v[j], q);
+      if (ra >= 0 && ra < n) Y1[ntile(c, ra, n, kNttYLogT)] = gl_add(v[j], q);
+      if (rb >= 0 && rb < n) Y1[ntile(c, rb, n, kNttYLogT)] = gl_sub(v[j], q);
     }
   }
 }
@@ -330,7 +332,8 @@ hipError_t launch_ntt_rows_fwd(const uint64_t* in, int W, int P, int w, int L, i
   const size_t lds = 8 * (size_t)N;
   hipError_t e = nset_lds((const void*)k_ntt_rows_fwd, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ntt_rows_fwd, dim3(count), dim3(T), lds, s, in, W, P, w, L, count,
+  const int grid = (count + 7) / 8 * 8;         // n_xcd_slot needs a multiple of 8
+  hipLaunchKernelGGL(k_ntt_rows_fwd, dim3(grid), dim3(T), lds, s, in, W, P, w, L, count,
                      gather_n, logN, out, rows_alloc, logT, st);
   return hipGetLastError();
 }

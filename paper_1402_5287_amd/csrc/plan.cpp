@@ -331,7 +331,8 @@ int ntt_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
   p->mv_scratch = z.mv_scratch;
   p->Hn = reinterpret_cast<uint64_t*>(plan_mem);
   uint64_t* H1 = reinterpret_cast<uint64_t*>(scratch);
-  e = launch_ntt_rows_fwd(h, W, p->P, z.w, z.L, rows, gather, z.logNz, H1, rows, 4, st, s);
+  e = launch_ntt_rows_fwd(h, W, p->P, z.w, z.L, rows, gather, z.logNz, H1, rows, kNttXLogT, st,
+                          s);
   if (e != hipSuccess) return status_from_hip(e, "ntt rows fwd (h)");
   const uint64_t scale = gold_inv(gold_mul((uint64_t)z.Nt, (uint64_t)z.Nz));
   e = launch_ntt_cols_plan(H1, rows, (int)z.Nz, z.logNt, scale, p->Hn, s);
@@ -346,7 +347,7 @@ int ntt_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus
   uint64_t* Y1 = reinterpret_cast<uint64_t*>(scratch + p->mv_scratch / 2);
   hipError_t e = mark(ev, 0, s);
   if (e == hipSuccess)
-    e = launch_ntt_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logNz, X1, n, 4, st, s);
+    e = launch_ntt_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logNz, X1, n, kNttXLogT, st, s);
   if (e != hipSuccess) return status_from_hip(e, "ntt rows fwd (x)");
   e = mark(ev, 1, s);
   if (e == hipSuccess) e = launch_ntt_cols_pass(X1, p->Hn, n, (int)p->Nz, p->logNt, Y1, s);
@@ -354,7 +355,7 @@ int ntt_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus
   const int rev = (p->kind == HMV_HANKEL) ? 0 : 1;
   e = mark(ev, 2, s);
   if (e == hipSuccess)
-    e = launch_ntt_rows_inv(Y1, n, p->logNz, p->L, p->w, p->P, W, rev, 4, y, st, s);
+    e = launch_ntt_rows_inv(Y1, n, p->logNz, p->L, p->w, p->P, W, rev, kNttYLogT, y, st, s);
   if (e == hipSuccess) e = mark(ev, 3, s);
   return status_from_hip(e, "ntt rows inv");
 }
