@@ -90,6 +90,28 @@ __device__ inline void load_words(const uint64_t* __restrict__ src, int W, uint6
   }
 }
 
+// load_words with `between()` run after the first loads are issued and
+// before their values reach LDS, so that independent LDS work overlaps the
+// global-memory latency.
+template <class F>
+__device__ __forceinline__ void load_words_then(const uint64_t* __restrict__ src, int W,
+                                                uint64_t* dst, F between) {
+  const int T = blockDim.x, t = threadIdx.x;
+  uint64_t r[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = t + u * T;
+    r[u] = src[q < W ? q : W - 1];
+  }
+  between();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int q = t + u * T;
+    if (q < W) dst[q] = r[u];
+  }
+  if (4 * T < W) load_words(src + 4 * T, W - 4 * T, dst + 4 * T);
+}
+
 // ---------------------------------------------------------------------------
 // block-wide exclusive scan of an associative operator on small codes.
 // op(a, b) means "a first, then b".  blockDim.x must be a multiple of 64.
@@ -158,6 +180,25 @@ __device__ inline bool number_in_range(const uint64_t* wd, int W, int P) {
   ok_hi = __syncthreads_and(ok_hi);
   ok_sp = __syncthreads_and(ok_sp);
   return ok_hi || ok_sp;
+}
+
+// number_in_range evaluated by the calling wavefront alone (its 64 lanes
+// stride over the words): no block barrier, so the other waves go on.
+__device__ inline bool number_in_range_wave(const uint64_t* wd, int W, int P) {
+  const uint64_t sign = (wd[W - 1] >> 63) ? ~0ull : 0ull;
+  int ok_hi = 1, ok_sp = (sign == 0ull);
+  for (int q = threadIdx.x & 63; q < W; q += 64) {
+    const uint64_t word = wd[q];
+    const int lo = q * 64;
+    uint64_t mask;
+    if (lo >= P) mask = ~0ull;
+    else if (P < lo + 64) mask = ~0ull << (P - lo);
+    else mask = 0ull;
+    if ((word & mask) != (sign & mask)) ok_hi = 0;
+    const uint64_t expect = (q == (P >> 6)) ? (1ull << (P & 63)) : 0ull;
+    if (word != expect) ok_sp = 0;
+  }
+  return __all(ok_hi) || __all(ok_sp);
 }
 
 // raw (unsigned) w-bit field e of the sign-extended two's complement number

@@ -181,16 +181,20 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   if (r >= count) return;
   const int T = blockDim.x, t = threadIdx.x;
   constexpr int M = 1 << LOGM;
-  const int src = gather_row(r, gather_n);
-  load_words(in + (int64_t)src * W, W, wd);
-  __syncthreads();
-  if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
   // digit e is the real (e even) or imaginary (e odd) part of element e/2;
   // the elements past the digits are zero (and the imaginary half of the
-  // last one when L is odd)
+  // last one when L is odd), written while the words are in flight
   double* bd = reinterpret_cast<double*>(buf);
-  for (int k = (L + 1) / 2 + t; k < M; k += T) buf[lds_slot(k)] = make_double2(0.0, 0.0);
-  if ((L & 1) && t == 0) bd[2 * lds_slot(L >> 1) + 1] = 0.0;
+  load_words_then(in + (int64_t)gather_row(r, gather_n) * W, W, wd, [&] {
+    for (int k = (L + 1) / 2 + t; k < M; k += T) buf[lds_slot(k)] = make_double2(0.0, 0.0);
+    if ((L & 1) && t == 0) bd[2 * lds_slot(L >> 1) + 1] = 0.0;
+  });
+  __syncthreads();
+  // range check by wave 0 alone (no block barrier)
+  if (t < 64) {
+    const bool ok = number_in_range_wave(wd, W, P);
+    if (!ok && t == 0) status_or(st, ST_RANGE);
+  }
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds_t<LOGM>(buf, -1);
@@ -642,13 +646,16 @@ __device__ __forceinline__ void b_row_fwd(const uint64_t* in, int W, int P, int 
                           uint32_t* red, DevStatus* st) {
   const int T = blockDim.x, t = threadIdx.x;
   const int M = 1 << logM;
-  const int src = gather_row(r, gather_n);
-  load_words(in + (int64_t)src * W, W, wd);
-  __syncthreads();
-  if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
   double* bd = reinterpret_cast<double*>(buf);
-  for (int k = (L + 1) / 2 + t; k < M; k += T) buf[lds_slot(k)] = make_double2(0.0, 0.0);
-  if ((L & 1) && t == 0) bd[2 * lds_slot(L >> 1) + 1] = 0.0;
+  load_words_then(in + (int64_t)gather_row(r, gather_n) * W, W, wd, [&] {
+    for (int k = (L + 1) / 2 + t; k < M; k += T) buf[lds_slot(k)] = make_double2(0.0, 0.0);
+    if ((L & 1) && t == 0) bd[2 * lds_slot(L >> 1) + 1] = 0.0;
+  });
+  __syncthreads();
+  if (t < 64) {
+    const bool ok = number_in_range_wave(wd, W, P);
+    if (!ok && t == 0) status_or(st, ST_RANGE);
+  }
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);

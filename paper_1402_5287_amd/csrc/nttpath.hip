@@ -83,11 +83,16 @@ __global__ void __launch_bounds__(512) k_ntt_rows_fwd(const uint64_t* __restrict
   if (r >= count) return;
   const int T = blockDim.x, t = threadIdx.x, N = 1 << logN;
   if (t < 16) r16[t] = g_nr16[t];
-  const int src = n_gather_row(r, gather_n);
-  load_words(in + (int64_t)src * W, W, wd);
+  // the residues past the digits are zeroed while the words are in flight;
+  // wave 0 alone checks the range (no block barrier)
+  load_words_then(in + (int64_t)n_gather_row(r, gather_n) * W, W, wd, [&] {
+    for (int e = L + t; e < N; e += T) nbuf[nswz(e)] = 0;
+  });
   __syncthreads();
-  if (!number_in_range(wd, W, P) && t == 0) status_or(st, ST_RANGE);
-  for (int e = L + t; e < N; e += T) nbuf[nswz(e)] = 0;
+  if (t < 64) {
+    const bool ok = number_in_range_wave(wd, W, P);
+    if (!ok && t == 0) status_or(st, ST_RANGE);
+  }
   split_balanced(wd, W, w, L, [&](int e, int d) { nbuf[nswz(e)] = gl_from_int(d); }, red);
   __syncthreads();
   ntt_lds(nbuf, logN, 0, r16);

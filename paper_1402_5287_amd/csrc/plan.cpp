@@ -618,7 +618,9 @@ int oneshot_planned(int kind, const uint64_t* h, const uint64_t* x, uint64_t* y,
   // one-shot calls reuse tuned launch variants but run no tuning of their own
   int rc = plan_h_impl(&p, kind, h, n, P, algo, base + align_up(wb), pb, base, wb, s, false);
   if (rc != HMV_OK) return rc;
-  rc = hmv_plan_matvec(p, x, y, base, wb, s);
+  // the status block keeps what the transform of h flagged (the NTT and
+  // Karatsuba plans do not read it back); the matvec adds its own flags
+  rc = plan_matvec_impl(p, x, y, base, wb, s, nullptr, false);
   hmv_plan_destroy(p);
   return rc;
 }
@@ -715,13 +717,24 @@ int hmv_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, void* ws,
 
 int hmv_plan_matvec_events(const hmv_plan* p, const uint64_t* x, uint64_t* y, void* ws,
                            int64_t ws_bytes, void* stream, void* const* events) {
+  return hmv::plan_matvec_impl(p, x, y, ws, ws_bytes, static_cast<hipStream_t>(stream), events,
+                               true);
+}
+
+}  // extern "C"
+
+namespace hmv {
+
+int plan_matvec_impl(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, void* ws,
+                     int64_t ws_bytes, hipStream_t s, void* const* events, bool clear) {
   if (!p || !x || !y || !ws) return HMV_EINVAL;
   if (ws_bytes < kStatusBytes) return HMV_ENOMEM;
   clear_stale_error();
-  hipStream_t s = static_cast<hipStream_t>(stream);
   DevStatus* st = static_cast<DevStatus*>(ws);
-  hipError_t e = launch_clear_status(st, s);
-  if (e != hipSuccess) return status_from_hip(e, "clear status");
+  if (clear) {
+    hipError_t e = launch_clear_status(st, s);
+    if (e != hipSuccess) return status_from_hip(e, "clear status");
+  }
   char* scratch = static_cast<char*>(ws) + kStatusBytes;
   const int64_t scratch_bytes = ws_bytes - kStatusBytes;
   if (p->algo == HMV_SPLIT_FFT)
@@ -731,6 +744,10 @@ int hmv_plan_matvec_events(const hmv_plan* p, const uint64_t* x, uint64_t* y, vo
     return kara_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);
   return HMV_EUNSUPPORTED;
 }
+
+}  // namespace hmv
+
+extern "C" {
 
 int64_t hmv_plan_workspace_bytes(const hmv_plan* p) {
   if (!p) return HMV_EINVAL;

@@ -70,6 +70,10 @@ int plan_h_impl(::hmv_plan** out, int kind, const uint64_t* h, int64_t n, int32_
                 bool may_tune);
 int oneshot_planned(int kind, const uint64_t* h, const uint64_t* x, uint64_t* y, int64_t n,
                     int32_t P, int algo, void* ws, int64_t ws_bytes, hipStream_t s);
+// hmv_plan_matvec_events; clear = false keeps the flags already in the
+// status block (a one-shot call's planning flags)
+int plan_matvec_impl(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, void* ws,
+                     int64_t ws_bytes, hipStream_t s, void* const* events, bool clear);
 
 }  // namespace hmv
 

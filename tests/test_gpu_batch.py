@@ -60,6 +60,32 @@ def test_batch_equals_single_paths_at_paper_sizes():
             assert np.array_equal(hmv.to_host(y), hankel.matvec_words(kname, h, x, P))
 
 
+def test_batch_out_of_range_flag():
+    """One member with an x entry just outside [-1, 1] sets the range flag of
+    the batch; the batch without it is clean."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    from oracle import fixedpoint as fp
+    specs = [(0, 40, 1024), (1, 7, 64), (2, 100, 3322)]
+    host, items = _make(specs, seed=7)
+    probs = hmv.batch_problems(items)
+    ws = hmv.workspace(hmv.batch_workspace_bytes(probs))
+    announce("batch range ok")
+    hmv.batch_matvec(probs, ws)
+    rc, flags, _ = hmv.read_status(ws)
+    assert rc == 0 and flags == 0
+    kname, h, x = host[1]
+    X = fp.decode(x)
+    X[3] = (1 << 64) + 1
+    bad = list(items)
+    bad[1] = (kname, items[1][1], hmv.to_device(fp.encode(X, 64)), items[1][3], 7, 64)
+    probs = hmv.batch_problems(bad)
+    announce("batch range bad")
+    hmv.batch_matvec(probs, ws)
+    rc, flags, _ = hmv.read_status(ws)
+    assert rc == hmv.ERANGE and (flags & 1)
+
+
 @pytest.mark.skip(reason="exercises the single-launch work-queue batch driver, which is switched "
                          "off: its one GPU run (and the run of its fix) did not finish within the "
                          "test time limit; see DESIGN.md")

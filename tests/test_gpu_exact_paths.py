@@ -52,6 +52,38 @@ def test_extremes_and_ties(algo):
             assert fp.decode(y) == [fp.round_half_even(hv << (P - 1), P)]
 
 
+@pytest.mark.parametrize("algo", ["split_fft", "ntt", "karatsuba"])
+def test_out_of_range_flag(algo):
+    """Inputs must lie in [-1, 1] (|X| <= 2^P).  The values +-1 and +-(1 - 2^-P)
+    pass; one step outside, in x or in h, sets the range flag and the call
+    returns HMV_ERANGE.  P covers a top word used in part and in full."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    n = 5
+    for P in (62, 64, 100, 3322):
+        lim = 1 << P
+        h = si.uniform(2 * n - 1, P, (80, P))
+        X = [lim, -lim, lim - 1, -(lim - 1), 0]
+        announce(algo, "range ok", P)
+        y, rc, flags = _oneshot("hankel", h, fp.encode(X, P), n, P, algo)
+        assert rc == 0 and flags == 0
+        assert np.array_equal(y, hankel.matvec_words("hankel", h, fp.encode(X, P), P))
+        for bad in (lim + 1, -(lim + 1), 2 * lim, -2 * lim):
+            announce(algo, "range x", P, bad > 0)
+            _, rc, flags = _oneshot("hankel", h, fp.encode([0, 0, bad, 0, 0], P), n, P, algo)
+            assert rc == hmv.ERANGE and (flags & 1), (P, bad)
+        H = fp.decode(h)
+        H[2 * n - 2] = -(lim + 1)
+        announce(algo, "range h", P)
+        # planning reads the flag of h at once: the call itself may return it
+        y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+        ws = hmv.workspace(hmv.oneshot_workspace_bytes("hankel", n, P, algo))
+        call_rc = hmv.matvec("hankel", hmv.to_device(fp.encode(H, P)), hmv.to_device(fp.encode(X, P)),
+                             y, n, P, algo=algo, ws=ws, check=False)
+        rc, flags, _ = hmv.read_status(ws)
+        assert hmv.ERANGE in (call_rc, rc) and (flags & 1)
+
+
 def test_karatsuba_matches_algorithm1_sizes():
     """Sizes where Algorithm 1's halving is uneven (m != m1) at several levels."""
     need_gpu()
