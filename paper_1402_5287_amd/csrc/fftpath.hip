@@ -399,10 +399,11 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
       maxerr = fmax(maxerr, fmax(fabs(v[j].x - r0), fabs(v[j].y - r1)));
       // every true coefficient is below 2^50 in magnitude (plan constraint)
       if (fabs(v[j].x) >= kCoefLimit || fabs(v[j].y) >= kCoefLimit) bad = 1;
-      if (2 * m < NC) coef[2 * m] = i0;
+      // one 16-byte store per pair; for odd NC the pair's second slot at NC
+      // lies in the padding before the carry scratch
+      if (2 * m < NC) *reinterpret_cast<longlong2*>(coef + 2 * m) = make_longlong2(i0, i1);
       else if (i0 != 0) bad = 1;
-      if (2 * m + 1 < NC) coef[2 * m + 1] = i1;
-      else if (i1 != 0) bad = 1;
+      if (2 * m + 1 >= NC && i1 != 0) bad = 1;
     }
   }
   row_status_publish(&rst, maxerr, bad, st);
