@@ -159,7 +159,7 @@ __device__ __forceinline__ void stockham_pass(double2* buf, int N, int Ns, int s
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          double2 w = tw[k * (R - 1) + (r - 1)];
+          double2 w = tw[(r - 1) * Ns + k];
           if (sign > 0) w.y = -w.y;
           v[i][r] = cmul(v[i][r], w);
         }
@@ -239,7 +239,7 @@ __device__ __forceinline__ void last_pass_to_regs(const double2* buf, int N, int
       u[r] = buf[(Ns & 15) == 0 ? lds_step(lds_slot(b), r, Ns) : lds_slot(b + r * Ns)];
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      double2 w = tw[b * (R - 1) + (r - 1)];
+      double2 w = tw[(r - 1) * Ns + b];
       if (sign > 0) w.y = -w.y;
       u[r] = cmul(u[r], w);
     }
@@ -310,7 +310,7 @@ __device__ __forceinline__ void fft_regs8(double2* v, double2* buf, int sign) {
       u[r] = buf[(Ta & 15) == 0 ? lds_step(lds_slot(t), r, Ta) : lds_slot(t + r * Ta)];
 #pragma unroll
     for (int r = 1; r < 8; ++r) {
-      double2 w = tw[t * 7 + (r - 1)];
+      double2 w = tw[(r - 1) * Ta + t];
       if (sign > 0) w.y = -w.y;
       u[r] = cmul(u[r], w);
     }

@@ -9,7 +9,9 @@ namespace hmv {
 // ---------------------------------------------------------------- twiddles
 // One table per (R, Ns), R in {2,4,8,16}, Ns in {1,8,16,64,256,512,4096}
 // (the spans of radix-16 passes and of radix-8 passes):
-// entries [k][r-1] = exp(-2 pi i r k / (R Ns)), k < Ns, 1 <= r < R.
+// entries [r-1][k] = exp(-2 pi i r k / (R Ns)), 1 <= r < R, k < Ns.  Root-major:
+// the lanes of a wave (consecutive k) read one root index from consecutive
+// entries, a few cache lines per load instead of one line per lane.
 constexpr int kTwSpans = 7;
 __host__ __device__ constexpr int tw_span(int b) {
   return b == 0 ? 1 : b == 1 ? 8 : b == 2 ? 16 : b == 3 ? 64 : b == 4 ? 256 : b == 5 ? 512 : 4096;

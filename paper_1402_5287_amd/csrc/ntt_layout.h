@@ -8,7 +8,9 @@ namespace hmv {
 
 constexpr uint64_t kGoldP = 0xFFFFFFFF00000001ull;
 
-// (R, Ns) tables as in the binary64 engine: entries [k][r-1] = w_{R Ns}^(r k)
+// (R, Ns) tables: entries [k][r-1] = w_{R Ns}^(r k), k < Ns, 1 <= r < R.  Unlike
+// the binary64 tables (root-major), a thread's R-1 roots of 8 bytes are
+// contiguous here, so that they load as a few wide loads.
 __host__ __device__ constexpr int64_t ntt_tw_offset(int R, int Ns) {
   int64_t off = 0;
   const int radices[4] = {2, 4, 8, 16};

@@ -66,8 +66,8 @@ double gen_fft_tables(double* tw, double* rtw) {
         for (int r = 1; r < R; ++r) {
           double re, im;
           unit_root((int64_t)r * k, (int64_t)R * Ns, &re, &im);
-          t[2 * (k * (R - 1) + (r - 1))] = re;
-          t[2 * (k * (R - 1) + (r - 1)) + 1] = im;
+          t[2 * ((r - 1) * Ns + k)] = re;
+          t[2 * ((r - 1) * Ns + k) + 1] = im;
           track((int64_t)r * k, (int64_t)R * Ns, re, im);
         }
     }

@@ -200,11 +200,12 @@ def test_planned_session_equals_exact_product():
     plan.close()
 
 
-@pytest.mark.parametrize("n,P", [(40, 700), (300, 2000), (3001, 700), (1000, 33220)])
+@pytest.mark.parametrize("n,P", [(40, 700), (200, 1500), (300, 2000), (3001, 700), (1000, 33220)])
 def test_every_launch_variant_is_exact(n, P):
     """Each launch variant the tuner may pick (radix-16 or radix-8 register
     transforms, XCD-grouped or linear columns) gives the exact words; the
-    shapes cover 64-, 512- and 4096-point index halves and limb transforms."""
+    shapes cover 64-, 256-, 512- and 4096-point index halves and limb
+    transforms."""
     need_gpu()
     from paper_1402_5287_amd import hmv
     h = si.uniform(2 * n - 1, P, (72, n))
