@@ -26,6 +26,14 @@ namespace hmv {
 // device with hipMemcpyToSymbol.
 __device__ double2 g_tw[kTwEntries];
 __device__ double2 g_rtw[kRealTwEntries];
+// the even entries of g_rtw (roots of order kRealTwN / 2), so that the
+// common even strides read consecutive entries
+__device__ double2 g_rtw2[kRealTwEntries2];
+
+// exp(-2 pi i k rs / kRealTwN)
+__device__ __forceinline__ double2 real_root(int k, int rs) {
+  return (rs & 1) ? g_rtw[k * rs] : g_rtw2[k * (rs >> 1)];
+}
 
 // ---------------------------------------------------------------- complex ops
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }

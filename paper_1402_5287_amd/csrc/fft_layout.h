@@ -29,4 +29,5 @@ constexpr int64_t kTwEntries = (1 + 3 + 7 + 15) * (1 + 8 + 16 + 64 + 256 + 512 +
 // real-input packing roots exp(-2 pi i k / 16384), k = 0..8192
 constexpr int kRealTwN = 16384;
 constexpr int64_t kRealTwEntries = kRealTwN / 2 + 1;
+constexpr int64_t kRealTwEntries2 = kRealTwN / 4 + 1;
 }  // namespace hmv

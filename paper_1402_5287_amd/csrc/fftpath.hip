@@ -34,13 +34,18 @@ namespace {
 std::mutex g_tab_mu;
 bool g_tab_ready[64] = {};
 double g_beta = -1.0;
-std::vector<double> g_tw_host, g_rtw_host;
+std::vector<double> g_tw_host, g_rtw_host, g_rtw2_host;
 
 void ensure_host_tables() {
   if (g_beta < 0.0) {
     g_tw_host.assign(2 * kTwEntries, 0.0);
     g_rtw_host.assign(2 * kRealTwEntries, 0.0);
     g_beta = gen_fft_tables(g_tw_host.data(), g_rtw_host.data());
+    g_rtw2_host.assign(2 * kRealTwEntries2, 0.0);
+    for (int64_t k = 0; k < kRealTwEntries2; ++k) {
+      g_rtw2_host[2 * k] = g_rtw_host[4 * k];
+      g_rtw2_host[2 * k + 1] = g_rtw_host[4 * k + 1];
+    }
   }
 }
 }  // namespace
@@ -62,6 +67,9 @@ hipError_t fft_tables_init() {
   e = hipMemcpyToSymbol(HIP_SYMBOL(g_tw), g_tw_host.data(), sizeof(double) * g_tw_host.size());
   if (e != hipSuccess) return e;
   e = hipMemcpyToSymbol(HIP_SYMBOL(g_rtw), g_rtw_host.data(), sizeof(double) * g_rtw_host.size());
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(g_rtw2), g_rtw2_host.data(),
+                        sizeof(double) * g_rtw2_host.size());
   if (e != hipSuccess) return e;
   g_tab_ready[dev] = true;
   return hipSuccess;
@@ -149,7 +157,7 @@ __device__ inline void pack_real_row(const double2* buf, int M, double2* __restr
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int k = k0 + u * T;
-      wv[u] = g_rtw[(k <= M ? k : M) * rs];
+      wv[u] = real_root(k <= M ? k : M, rs);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -242,7 +250,7 @@ __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H
         const double2 hi = col[(int64_t)(s + Nh < rows ? s + Nh : 0) * kX1Tile];
         const double2 l = s < rows ? lo : make_double2(0.0, 0.0);
         const double2 u = s + Nh < rows ? hi : make_double2(0.0, 0.0);
-        v[j] = half == 0 ? cadd(l, u) : cmul(csub(l, u), g_rtw[s * rs]);
+        v[j] = half == 0 ? cadd(l, u) : cmul(csub(l, u), real_root(s, rs));
       }
     }
     fft_regs<LOGNH>(v, buf, -1);
@@ -310,7 +318,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
         const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * kX1Tile];
         o[j] = s < n ? xv : make_double2(0.0, 0.0);
       }
-      o[j] = cmul(o[j], g_rtw[s * rs]);
+      o[j] = cmul(o[j], real_root(s, rs));
     }
   }
   fft_regs_r<LOGNH, R>(o, buf, -1);
@@ -324,7 +332,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
 #pragma unroll
     for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
-      const double2 q = cmul(o[j], conj2(g_rtw[s * rs]));
+      const double2 q = cmul(o[j], conj2(real_root(s, rs)));
       const int ra = s - (n - 1), rb = s + Nh - (n - 1);
       if (ra >= 0 && ra < n) ycol[(int64_t)ra * kY1Tile] = cadd(v[j], q);
       if (rb >= 0 && rb < n) ycol[(int64_t)rb * kY1Tile] = csub(v[j], q);
@@ -364,7 +372,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
     for (int j = 0; j < per; ++j) {
       const int k = t + Ta * j;
       v[j] = Y1[tidx<kY1Tile>(k, i, n)];
-      wk[j] = conj2(g_rtw[k * rs]);
+      wk[j] = conj2(real_root(k, rs));
     }
 #pragma unroll
     for (int j = 0; j < per; ++j) buf[lds_slot(t + Ta * j)] = v[j];
@@ -688,7 +696,7 @@ __device__ __forceinline__ void b_col_plan(const double2* H1, int rows, int logN
         if (s < Nh) {
           const double2 l = s < rows ? lo[u] : make_double2(0.0, 0.0);
           const double2 h = s + Nh < rows ? hi[u] : make_double2(0.0, 0.0);
-          buf[lds_slot(s)] = half == 0 ? cadd(l, h) : cmul(csub(l, h), g_rtw[s * rs]);
+          buf[lds_slot(s)] = half == 0 ? cadd(l, h) : cmul(csub(l, h), real_root(s, rs));
         }
       }
     }
@@ -727,7 +735,7 @@ __device__ __forceinline__ void b_col_pass(const double2* X1, const double2* Hh,
       if (s < Nh) {
         const double2 v = s < n ? xv[u] : make_double2(0.0, 0.0);
         be[lds_slot(s)] = v;
-        bo[lds_slot(s)] = cmul(v, g_rtw[s * rs]);
+        bo[lds_slot(s)] = cmul(v, real_root(s, rs));
       }
     }
   }
@@ -757,7 +765,7 @@ __device__ __forceinline__ void b_col_pass(const double2* X1, const double2* Hh,
   double2* ycol = Y1 + tile_index(c, 0, n);
   for (int s = t; s < Nh; s += T) {
     const double2 e = be[lds_slot(s)];
-    const double2 q = cmul(bo[lds_slot(s)], conj2(g_rtw[s * rs]));
+    const double2 q = cmul(bo[lds_slot(s)], conj2(real_root(s, rs)));
     const int ra = s - (n - 1), rb = s + Nh - (n - 1);
     if (ra >= 0 && ra < n) ycol[(int64_t)ra * 8] = cadd(e, q);
     if (rb >= 0 && rb < n) ycol[(int64_t)rb * 8] = csub(e, q);
@@ -799,7 +807,7 @@ __device__ __forceinline__ void b_row_inv(const double2* Y1, int n, int logM, in
       const double2 yk = buf[lds_slot(k)];
       const double2 ym = k == 0 ? ytop : buf[lds_slot(M - k)];
       const double2 E = cadd(yk, conj2(ym)), D = csub(yk, conj2(ym));
-      const double2 Q = cmul(D, conj2(g_rtw[k * rs]));
+      const double2 Q = cmul(D, conj2(real_root(k, rs)));
       z[a] = make_double2(E.x - Q.y, E.y + Q.x);
     }
   }
