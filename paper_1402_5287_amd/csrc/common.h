@@ -318,30 +318,38 @@ __host__ __device__ inline int carry_lds_bytes(int T) { return 8 * T + 64; }
 // (only for very large P at small widths) runs the same passes from LDS.
 constexpr int kCarryRegs = 32;
 
+// chunk length of carry_round_pack for NC coefficients over T threads
+__host__ __device__ inline int carry_chunk(int NC, int w, int T) {
+  const int kmin = (60 + w - 1) / w;
+  int E = (NC + T - 1) / T;
+  if (E < kmin) E = kmin;
+  return E | 1;
+}
+
+// REGS: limbs per thread held in registers (the unrolled length of the
+// chunk loops); carry_round_pack_fit picks the smallest that holds a chunk.
+template <int REGS>
 __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, int P, int W, int64_t* cs,
                                         uint64_t* __restrict__ y, uint32_t* red) {
   const int T = blockDim.x, t = threadIdx.x;
   const int64_t mask = (int64_t(1) << w) - 1;
-  const int kmin = (60 + w - 1) / w;
-  int E = (NC + T - 1) / T;
-  if (E < kmin) E = kmin;
-  E |= 1;
+  const int E = carry_chunk(NC, w, T);
   const int nch = (NC + E - 1) / E;
   const int e0 = t * E, e1 = min(NC, e0 + E);
   const bool own = t < nch;
   const int len = own ? e1 - e0 : 0;
-  const bool in_regs = E <= kCarryRegs;         // uniform
-  int64_t r[kCarryRegs];
+  const bool in_regs = E <= REGS;         // uniform
+  int64_t r[REGS];
   // 1. chunk-local normalisation
   int64_t cown = 0;
   if (in_regs) {
 #pragma unroll
-    for (int j = 0; j < kCarryRegs; ++j) {
+    for (int j = 0; j < REGS; ++j) {
       const int e = e0 + j < NC ? e0 + j : NC - 1;
       r[j] = coef[e];
     }
 #pragma unroll
-    for (int j = 0; j < kCarryRegs; ++j) {
+    for (int j = 0; j < REGS; ++j) {
       const int64_t c = r[j] + cown;
       const bool in = j < len;
       r[j] = in ? (c & mask) : 0;
@@ -366,7 +374,7 @@ __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, i
     int64_t cm = cin - 1, c0 = cin, cp = cin + 1;
     if (in_regs) {
 #pragma unroll
-      for (int j = 0; j < kCarryRegs; ++j) {
+      for (int j = 0; j < REGS; ++j) {
         const bool in = j < len;
         cm = in ? (r[j] + cm) >> w : cm;
         c0 = in ? (r[j] + c0) >> w : c0;
@@ -390,7 +398,7 @@ __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, i
   int st = 0;
   if (in_regs) {
 #pragma unroll
-    for (int j = 0; j < kCarryRegs; ++j) {
+    for (int j = 0; j < REGS; ++j) {
       const int64_t c = r[j] + carry;
       const bool in = j < len;
       r[j] = c & mask;
@@ -401,7 +409,7 @@ __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, i
     }
     if (own) {
 #pragma unroll
-      for (int j = 0; j < kCarryRegs; ++j)
+      for (int j = 0; j < REGS; ++j)
         if (j < len) coef[e0 + j] = r[j];
     }
   } else if (own) {
@@ -466,6 +474,15 @@ __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, i
       y[m] = m < first ? 0ull : word_at(P + 64 * m) + 1ull;
   }
   __syncthreads();
+}
+
+template <class... A>
+__device__ __forceinline__ void carry_round_pack_fit(int64_t* coef, int NC, int w, A... rest) {
+  const int E = carry_chunk(NC, w, blockDim.x);     // uniform
+  if (E <= 9) carry_round_pack<9>(coef, NC, w, rest...);
+  else if (E <= 17) carry_round_pack<17>(coef, NC, w, rest...);
+  else if (E <= 25) carry_round_pack<25>(coef, NC, w, rest...);
+  else carry_round_pack<kCarryRegs>(coef, NC, w, rest...);
 }
 
 }  // namespace hmv

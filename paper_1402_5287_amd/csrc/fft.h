@@ -23,12 +23,13 @@ namespace hmv {
 
 // The tables live in the code object of the one translation unit that
 // includes this header (the split-FFT kernels); the host fills them once per
-// device with hipMemcpyToSymbol.
-__device__ double2 g_tw[kTwEntries];
-__device__ double2 g_rtw[kRealTwEntries];
+// device with hipMemcpyToSymbol.  Page-aligned, so that where they land does
+// not depend on the size of the code around them.
+__device__ __align__(4096) double2 g_tw[kTwEntries];
+__device__ __align__(4096) double2 g_rtw[kRealTwEntries];
 // the even entries of g_rtw (roots of order kRealTwN / 2), so that the
 // common even strides read consecutive entries
-__device__ double2 g_rtw2[kRealTwEntries2];
+__device__ __align__(4096) double2 g_rtw2[kRealTwEntries2];
 
 // exp(-2 pi i k rs / kRealTwN)
 __device__ __forceinline__ double2 real_root(int k, int rs) {

@@ -417,7 +417,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
   row_status_publish(&rst, maxerr, bad, st);
   int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
   const int row = out_reverse ? (n - 1 - i) : i;
-  carry_round_pack(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
+  carry_round_pack_fit(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -848,7 +848,7 @@ __device__ __forceinline__ void b_row_inv(const double2* Y1, int n, int logM, in
   const int carry_off = (NC * 8 + 15) / 16 * 16;
   int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
   const int row = out_reverse ? (n - 1 - i) : i;
-  carry_round_pack(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
+  carry_round_pack_fit(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
 __global__ void __launch_bounds__(256) k_batch(const BatchInst* __restrict__ inst,

@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(512) k_ntt_rows_inv(const uint64_t* __restrict
   if (bad && t == 0) status_or(st, ST_BOUND);
   int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(nbuf) + carry_off);
   const int row = out_reverse ? (n - 1 - i) : i;
-  carry_round_pack(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
+  carry_round_pack_fit(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
 // ------------------------------------------------------------------ columns

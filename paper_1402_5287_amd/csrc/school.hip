@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(512) k_school_row(const double* __restrict__ h
   }
   __syncthreads();
   const int row = out_reverse ? (n - 1 - i) : i;
-  carry_round_pack(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
+  carry_round_pack_fit(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
 size_t school_lds_bytes(int L, int w, int P, int W) {
