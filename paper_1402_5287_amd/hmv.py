@@ -21,6 +21,7 @@ AUTO, SPLIT_FFT, NTT, KARATSUBA, SCHOOLBOOK = 0, 1, 2, 3, 4
 ALGOS = {"auto": AUTO, "split_fft": SPLIT_FFT, "ntt": NTT, "karatsuba": KARATSUBA,
          "schoolbook": SCHOOLBOOK}
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EBOUND, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+MAX_P, MAX_N = 40960, 16384          # HMV_MAX_P, HMV_MAX_N
 
 _c_i64, _c_i32, _c_int, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p
 

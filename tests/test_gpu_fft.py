@@ -156,6 +156,25 @@ def test_index_axis_16384():
     assert np.array_equal(yt, y[::-1])
 
 
+@pytest.mark.parametrize("algo", ["split_fft", "ntt"])
+def test_largest_planned_sizes(algo):
+    """The largest shapes of the planned paths: n = 8192 (index axis of 16384
+    points) at the paper's P, and P = HMV_MAX_P (40960 bits) at n = 4096.
+    Sampled rows against the oracle; the Toeplitz product of the same data is
+    the Hankel output reversed."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    for n, P in ((8192, 33220), (4096, hmv.MAX_P)):
+        h = si.uniform(2 * n - 1, P, (74, n, P))
+        x = si.uniform(n, P, (75, n, P))
+        announce("fft largest", algo, n, P)
+        y, rc, flags, err = _oneshot("hankel", h, x, n, P, algo=algo)
+        assert rc == 0 and flags == 0
+        _sampled_rows_check(h, x, y, P, [0, 1, n // 2, n - 2, n - 1])
+        yt, rc, _, _ = _oneshot("toeplitz", h, x, n, P, algo=algo)
+        assert rc == 0 and np.array_equal(yt, y[::-1])
+
+
 def test_index_axis_8192_ragged_all_kinds():
     """2048 < n < 4096: an 8192-point index axis with a ragged window, every
     kind, against the exact GMP product (and sampled schoolbook rows)."""

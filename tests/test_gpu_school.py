@@ -78,6 +78,22 @@ def test_basis_vectors_bit_exact():
         assert fp.decode(y) == H[k:k + n]
 
 
+def test_largest_n():
+    """n = HMV_MAX_N (16384), the schoolbook's limit, at a one-word precision;
+    sampled rows against the oracle."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    n, P = hmv.MAX_N, 64
+    h = si.uniform(2 * n - 1, P, (76,))
+    x = si.uniform(n, P, (77,))
+    announce("school largest n", n, P)
+    y, rc, flags = _run("hankel", h, x, n, P)
+    assert rc == 0 and flags == 0
+    rows = [0, 1, n // 2, n - 1]
+    H, X = fp.decode(h), fp.decode(x)
+    assert fp.decode(y[rows]) == hankel.matvec_rows("hankel", H, X, P, rows, processes=4)
+
+
 def test_out_of_range_flag():
     need_gpu()
     n, P = 4, 100

@@ -55,6 +55,20 @@ def test_size_queries():
     assert L.hmv_oneshot_workspace_bytes(0, 64, 3322, 4) > 0
 
 
+def test_planned_paths_size_limit():
+    """The planned paths take n up to 8192 (index axis of 16384 points); larger
+    n up to HMV_MAX_N is refused with HMV_EUNSUPPORTED, except by the
+    schoolbook, which takes every n up to HMV_MAX_N."""
+    hmv, L = _lib()
+    for algo in (0, 1, 2, 3):
+        assert L.hmv_oneshot_workspace_bytes(0, 8192, 3322, algo) > 0
+        assert L.hmv_oneshot_workspace_bytes(0, 8193, 3322, algo) == hmv.EUNSUPPORTED
+        assert L.hmv_plan_bytes(0, 8193, 3322, algo) == hmv.EUNSUPPORTED
+    assert L.hmv_words(hmv.MAX_P) > 0 and L.hmv_words(hmv.MAX_P + 1) == hmv.EINVAL
+    assert L.hmv_oneshot_workspace_bytes(0, hmv.MAX_N, 3322, 4) > 0
+    assert L.hmv_oneshot_workspace_bytes(0, hmv.MAX_N + 1, 3322, 4) == hmv.EINVAL
+
+
 def _percival(na, nb, k, beta):
     """Independent evaluation with exact rationals for the powers and a
     rigorous upper rounding of the result."""
