@@ -90,7 +90,7 @@ __device__ __forceinline__ int xcd_slot(int b, int grid) {
 #define HMV_X1_TILE 2
 #endif
 #ifndef HMV_Y1_TILE
-#define HMV_Y1_TILE 8
+#define HMV_Y1_TILE 4
 #endif
 constexpr int kX1Tile = HMV_X1_TILE;   // spectra of x (and of h while planning)
 constexpr int kY1Tile = HMV_Y1_TILE;   // spectra of y
@@ -355,7 +355,8 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
   __shared__ uint32_t red[32];
   __shared__ RowStatus rst;
   __shared__ double2 ytop;                 // Y[M]
-  const int i = blockIdx.x;
+  // rows grouped per XCD: consecutive rows share the lines of a Y1 tile
+  const int i = xcd_slot(blockIdx.x, gridDim.x);
   if (i >= n) return;
   row_status_init(&rst);
   constexpr int M = 1 << LOGM;
@@ -564,7 +565,8 @@ hipError_t rows_inv_r(const double2* Y1, int n, int L, int w, int P, int W, int 
   const size_t lds = fft_part > carry_part ? fft_part : carry_part;
   hipError_t e = set_lds((const void*)k_rows_inv<LOGM, R>, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_rows_inv<LOGM, R>), dim3(n), dim3(T), lds, s, Y1, n, L, w, P, W,
+  const int grid = (n + 7) / 8 * 8;             // xcd_slot needs a multiple of 8
+  hipLaunchKernelGGL((k_rows_inv<LOGM, R>), dim3(grid), dim3(T), lds, s, Y1, n, L, w, P, W,
                      out_reverse, (int)carry_off, y, st);
   return hipGetLastError();
 }
