@@ -327,7 +327,9 @@ __host__ __device__ inline int carry_chunk(int NC, int w, int T) {
 }
 
 // REGS: limbs per thread held in registers (the unrolled length of the
-// chunk loops); carry_round_pack_fit picks the smallest that holds a chunk.
+// chunk loops); carry_round_pack_fit picks the smallest of 9, 13, 17, 25 and
+// 32 that holds a chunk (13 and 25 are the chunks of the 4096-point inverse
+// pass at 512 and 256 threads).
 template <int REGS>
 __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, int P, int W, int64_t* cs,
                                         uint64_t* __restrict__ y, uint32_t* red) {
@@ -480,6 +482,7 @@ template <class... A>
 __device__ __forceinline__ void carry_round_pack_fit(int64_t* coef, int NC, int w, A... rest) {
   const int E = carry_chunk(NC, w, blockDim.x);     // uniform
   if (E <= 9) carry_round_pack<9>(coef, NC, w, rest...);
+  else if (E <= 13) carry_round_pack<13>(coef, NC, w, rest...);
   else if (E <= 17) carry_round_pack<17>(coef, NC, w, rest...);
   else if (E <= 25) carry_round_pack<25>(coef, NC, w, rest...);
   else carry_round_pack<kCarryRegs>(coef, NC, w, rest...);
