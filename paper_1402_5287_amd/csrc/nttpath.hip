@@ -43,8 +43,12 @@ hipError_t ntt_tables_init() {
   if (g_ntab_ready[dev]) return hipSuccess;
   std::vector<uint64_t> tw(2 * kNttTwEntries), r16(32), split(2 * kNttSplitEntries);
   gen_ntt_tables(tw.data(), r16.data(), split.data());
+  // the device applies the radix-16 internal roots as powers of two
+  for (int m = 0; m < 16; ++m)
+    if (r16[m] != gold_pow(2, (uint64_t)r16_exp<0>(m)) ||
+        r16[16 + m] != gold_pow(2, (uint64_t)r16_exp<1>(m)))
+      return hipErrorInvalidValue;
   e = hipMemcpyToSymbol(HIP_SYMBOL(g_ntw), tw.data(), 8 * tw.size());
-  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_nr16), r16.data(), 8 * r16.size());
   if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_nsplit), split.data(), 8 * split.size());
   if (e != hipSuccess) return e;
   g_ntab_ready[dev] = true;
@@ -76,13 +80,11 @@ __global__ void __launch_bounds__(512) k_ntt_rows_fwd(const uint64_t* __restrict
   extern __shared__ uint64_t nbuf[];
   __shared__ uint64_t wd[kMaxWords];
   __shared__ uint32_t red[32];
-  __shared__ uint64_t r16[16];
   // rows grouped per XCD, so that the rows sharing the lines of a tile
   // column are written through one L2
   const int r = n_xcd_slot(blockIdx.x, gridDim.x);
   if (r >= count) return;
   const int T = blockDim.x, t = threadIdx.x, N = 1 << logN;
-  if (t < 16) r16[t] = g_nr16[t];
   // the residues past the digits are zeroed while the words are in flight;
   // wave 0 alone checks the range (no block barrier)
   load_words_then(in + (int64_t)n_gather_row(r, gather_n) * W, W, wd, [&] {
@@ -95,7 +97,7 @@ __global__ void __launch_bounds__(512) k_ntt_rows_fwd(const uint64_t* __restrict
   }
   split_balanced(wd, W, w, L, [&](int e, int d) { nbuf[nswz(e)] = gl_from_int(d); }, red);
   __syncthreads();
-  ntt_lds(nbuf, logN, 0, r16);
+  ntt_lds<0>(nbuf, logN);
   for (int k = t; k < N; k += T) out[ntile(k, r, rows_alloc, logT)] = nbuf[nswz(k)];
 }
 
@@ -107,11 +109,9 @@ __global__ void __launch_bounds__(512) k_ntt_rows_inv(const uint64_t* __restrict
                                                       uint64_t* __restrict__ y, DevStatus* st) {
   extern __shared__ uint64_t nbuf[];
   __shared__ uint32_t red[32];
-  __shared__ uint64_t r16[16];
   const int i = blockIdx.x;
   if (i >= n) return;
   const int T = blockDim.x, t = threadIdx.x, N = 1 << logN;
-  if (t < 16) r16[t] = g_nr16[16 + t];
   {
     // element k = t + T a; the loads of a thread are issued together
     uint64_t ld[16];
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(512) k_ntt_rows_inv(const uint64_t* __restrict
     }
   }
   __syncthreads();
-  ntt_lds(nbuf, logN, 1, r16);
+  ntt_lds<1>(nbuf, logN);
   const int NC = 2 * L - 1;
   int bad = 0;
   // centre every residue; coefficients past NC must vanish
@@ -165,7 +165,6 @@ __global__ void __launch_bounds__(512) k_ntt_cols_plan(const uint64_t* __restric
                                                        int C, uint64_t scale,
                                                        uint64_t* __restrict__ Hh) {
   extern __shared__ uint64_t nbuf[];
-  __shared__ uint64_t r16[16];
   const int c = n_xcd_slot(blockIdx.x, gridDim.x);
   if (c >= C) return;
   constexpr int logNt = LOGNH + 1, Nh = 1 << LOGNH;
@@ -173,8 +172,6 @@ __global__ void __launch_bounds__(512) k_ntt_cols_plan(const uint64_t* __restric
   constexpr int ss = kNttSplitN >> logNt;
   const int t = threadIdx.x;
   const bool act = t < Ta;
-  if (t < 16) r16[t] = g_nr16[t];
-  __syncthreads();
   uint64_t* he = Hh + (int64_t)c * (2 * Nh);
   uint64_t v[16];
   for (int half = 0; half < 2; ++half) {
@@ -189,7 +186,7 @@ __global__ void __launch_bounds__(512) k_ntt_cols_plan(const uint64_t* __restric
         v[j] = half == 0 ? gl_add(lo, hi) : gl_mul(gl_sub(lo, hi), g_nsplit[s * ss]);
       }
     }
-    ntt_regs<LOGNH>(v, nbuf, 0, r16);
+    ntt_regs<LOGNH, 0>(v, nbuf);
     uint64_t* dst = he + half * Nh;
     if (act) {
 #pragma unroll
@@ -203,7 +200,6 @@ __global__ void __launch_bounds__(512) k_ntt_cols_pass(const uint64_t* __restric
                                                        const uint64_t* __restrict__ Hh, int n,
                                                        int C, uint64_t* __restrict__ Y1) {
   extern __shared__ uint64_t nbuf[];
-  __shared__ uint64_t r16f[16], r16i[16];
   const int c = n_xcd_slot(blockIdx.x, gridDim.x);
   if (c >= C) return;
   constexpr int logNt = LOGNH + 1, Nh = 1 << LOGNH;
@@ -211,10 +207,6 @@ __global__ void __launch_bounds__(512) k_ntt_cols_pass(const uint64_t* __restric
   constexpr int ss = kNttSplitN >> logNt;
   const int t = threadIdx.x;
   const bool act = t < Ta;
-  if (t < 16) {
-    r16f[t] = g_nr16[t];
-    r16i[t] = g_nr16[16 + t];
-  }
   const uint64_t* he = Hh + (int64_t)c * (2 * Nh);
   const uint64_t* ho = he + Nh;
   // The column is read once (o keeps it for the odd half); every
@@ -231,22 +223,22 @@ __global__ void __launch_bounds__(512) k_ntt_cols_pass(const uint64_t* __restric
     }
   }
   __syncthreads();
-  ntt_regs<LOGNH>(v, nbuf, 0, r16f);
+  ntt_regs<LOGNH, 0>(v, nbuf);
   if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) v[j] = gl_mul(v[j], he[t + Ta * j]);
   }
-  ntt_regs<LOGNH>(v, nbuf, 1, r16i);
+  ntt_regs<LOGNH, 1>(v, nbuf);
   if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) o[j] = gl_mul(o[j], g_nsplit[(t + Ta * j) * ss]);
   }
-  ntt_regs<LOGNH>(o, nbuf, 0, r16f);
+  ntt_regs<LOGNH, 0>(o, nbuf);
   if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) o[j] = gl_mul(o[j], ho[t + Ta * j]);
   }
-  ntt_regs<LOGNH>(o, nbuf, 1, r16i);
+  ntt_regs<LOGNH, 1>(o, nbuf);
   if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) {
