@@ -70,8 +70,10 @@ hipError_t launch_ntt_cols_pass(const uint64_t* X1, const uint64_t* Hh, int n, i
                                 uint64_t* Y1, hipStream_t s);
 hipError_t launch_kara_rowops(const int4* ops, int nops, const uint64_t* src, uint64_t* dst,
                               int Nz, hipStream_t s);
-hipError_t launch_kara_leaves(const int4* rows, int nrows, const uint64_t* A, const uint64_t* X,
-                              uint64_t* Y, int Nz, hipStream_t s);
+// leaves: (first A row, first X row, first Y row, size m <= kKaraWindow)
+constexpr int kKaraWindow = 32;
+hipError_t launch_kara_leaves(const int4* leaves, int nleaves, const uint64_t* A,
+                              const uint64_t* X, uint64_t* Y, int Nz, hipStream_t s);
 hipError_t launch_ntt_scale(uint64_t* a, int64_t count, uint64_t scale, hipStream_t s);
 
 }  // namespace hmv

@@ -268,22 +268,60 @@ __global__ void __launch_bounds__(256) k_kara_rowops(const int4* __restrict__ op
   dst[(int64_t)op.x * Nz + k] = op.w > 0 ? gl_add(a, b) : gl_sub(a, b);
 }
 
-// Leaf products: for each entry (a row, x row, y row, m) of leaf rows,
-// y[y] = sum_{j < m} A[a + j] * X[x + j] per column (a Hankel row of a
-// leaf: a = leaf a-offset + i, y = leaf y-offset + i).
-__global__ void __launch_bounds__(256) k_kara_leaves(const int4* __restrict__ rows, int nrows,
+// Leaf products: for a leaf (a, x, y, m), the plain Hankel product
+//   Y[y + i] = sum_{j < m} A[a + i + j] X[x + j],  i < m,
+// per column k (the limb-NTT domain is pointwise).  One thread per (leaf,
+// column) keeps a window of kKaraWindow A values and m accumulators in
+// registers: step j multiplies X[x + j] into every accumulator, then slides
+// the window by one row, so each A and X value is read once.  The products
+// are summed unreduced as 128-bit values with a count of the carries out of
+// bit 127 (m <= 32 products stay below 2^133), and reduced once per output:
+// 2^64 = 2^32 - 1 and 2^128 = -2^32 (mod p).
+__global__ void __launch_bounds__(256) k_kara_leaves(const int4* __restrict__ leaves, int nleaves,
                                                      const uint64_t* __restrict__ A,
                                                      const uint64_t* __restrict__ X,
                                                      uint64_t* __restrict__ Yo, int Nz) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)nrows * Nz;
+  const int64_t total = (int64_t)nleaves * Nz;
   if (gid >= total) return;
   const int o = (int)(gid / Nz), k = (int)(gid % Nz);
-  const int4 lr = rows[o];
-  uint64_t acc = 0;
-  for (int j = 0; j < lr.w; ++j)
-    acc = gl_add(acc, gl_mul(A[(int64_t)(lr.x + j) * Nz + k], X[(int64_t)(lr.y + j) * Nz + k]));
-  Yo[(int64_t)lr.z * Nz + k] = acc;
+  const int4 lf = leaves[o];
+  const int a = lf.x, x = lf.y, yr = lf.z, m = lf.w;
+  constexpr int Wn = kKaraWindow;
+  uint64_t win[Wn], lo[Wn], hi[Wn];
+  uint32_t top[Wn];
+#pragma unroll
+  for (int i = 0; i < Wn; ++i) {
+    win[i] = i < 2 * m - 1 ? A[(int64_t)(a + i) * Nz + k] : 0;
+    lo[i] = hi[i] = 0;
+    top[i] = 0;
+  }
+  for (int j = 0; j < m; ++j) {
+    const uint64_t xj = X[(int64_t)(x + j) * Nz + k];
+    const uint64_t nxt = j + Wn <= 2 * m - 2 ? A[(int64_t)(a + j + Wn) * Nz + k] : 0;
+#pragma unroll
+    for (int i = 0; i < Wn; ++i) {
+      if (i < m) {
+        const uint64_t pl = win[i] * xj, ph = __umul64hi(win[i], xj);
+        const uint64_t l2 = lo[i] + pl;
+        const uint64_t h1 = hi[i] + ph;
+        const uint64_t h2 = h1 + (l2 < pl ? 1ull : 0ull);
+        top[i] += (h1 < ph ? 1u : 0u) + (h2 < h1 ? 1u : 0u);
+        lo[i] = l2;
+        hi[i] = h2;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i + 1 < Wn; ++i) win[i] = win[i + 1];
+    win[Wn - 1] = nxt;
+  }
+#pragma unroll
+  for (int i = 0; i < Wn; ++i)
+    if (i < m) {
+      // lo + hi 2^64 + top 2^128 = fold(lo, hi) - top 2^32  (mod p)
+      const uint64_t f = gl_fold(lo[i], hi[i]);
+      Yo[(int64_t)(yr + i) * Nz + k] = gl_sub(f, (uint64_t)top[i] << 32);
+    }
 }
 
 // Scale whole rows by a residue (the 1 / N_z of the inverse limb transform).
@@ -412,12 +450,12 @@ hipError_t launch_kara_rowops(const int4* ops, int nops, const uint64_t* src, ui
   return hipGetLastError();
 }
 
-hipError_t launch_kara_leaves(const int4* rows, int nrows, const uint64_t* A, const uint64_t* X,
-                              uint64_t* Y, int Nz, hipStream_t s) {
-  if (nrows <= 0) return hipSuccess;
-  const int64_t total = (int64_t)nrows * Nz;
+hipError_t launch_kara_leaves(const int4* leaves, int nleaves, const uint64_t* A,
+                              const uint64_t* X, uint64_t* Y, int Nz, hipStream_t s) {
+  if (nleaves <= 0) return hipSuccess;
+  const int64_t total = (int64_t)nleaves * Nz;
   const int grid = (int)((total + 255) / 256);
-  hipLaunchKernelGGL(k_kara_leaves, dim3(grid), dim3(256), 0, s, rows, nrows, A, X, Y, Nz);
+  hipLaunchKernelGGL(k_kara_leaves, dim3(grid), dim3(256), 0, s, leaves, nleaves, A, X, Y, Nz);
   return hipGetLastError();
 }
 

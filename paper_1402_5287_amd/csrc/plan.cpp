@@ -361,6 +361,7 @@ int ntt_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus
 }
 
 // ---- Karatsuba (Section 4, Algorithm 1) over the index axis
+static_assert(kKaraLeaf <= kKaraWindow, "a leaf must fit the leaf kernel's window");
 struct KaraTree {
   int depth = 0;
   int64_t rowsA = 0, rowsX = 0, rowsY = 0;
@@ -391,8 +392,7 @@ KaraTree kara_build(int64_t n, int leaf_max) {
     for (const Node& nd : level) {
       const int64_t m = nd.m;
       if (m <= leaf_max) {
-        for (int64_t i = 0; i < m; ++i)
-          T.leaf.push_back(make_int4((int)(nd.a + i), (int)nd.x, (int)(nd.y + i), (int)m));
+        T.leaf.push_back(make_int4((int)nd.a, (int)nd.x, (int)nd.y, (int)m));
         T.mults += m * m;
         continue;
       }

@@ -98,7 +98,7 @@ struct hmv_plan {
   int64_t rowsA = 0, rowsX = 0, rowsY = 0;
   const int4* d_xops = nullptr;     // x-side splits, all levels
   const int4* d_cops = nullptr;     // combines, all levels
-  const int4* d_leaf = nullptr;     // leaf rows
+  const int4* d_leaf = nullptr;     // leaves (A row, X row, Y row, size)
   std::vector<int> xops_off, xops_cnt, cops_off, cops_cnt;
   int nleaf = 0;
   int64_t leaves_mults = 0;         // scalar products per limb column (Algorithm 1 count)
