@@ -3,18 +3,49 @@
 
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "fft_layout.h"
 #include "ntt_layout.h"
 
 namespace hmv {
 
-void unit_root(int64_t m, int64_t N, double* re, double* im) {
+namespace {
+constexpr long double kPiL = 3.141592653589793238462643383279502884L;
+
+// cos and sin (long double) of the first-octant angles 2 pi r / kRootRes,
+// r = 0 .. kRootRes / 8.  Every table size N divides kRootRes, and for N a
+// power of two the angle 2 pi r / N is computed to the same long double as
+// 2 pi (r kRootRes / N) / kRootRes (scaling by a power of two is exact), so
+// the roots come out bit for bit as if evaluated directly; the cosines and
+// sines are evaluated once each instead of once per table entry.
+constexpr int64_t kRootRes = 65536;
+struct Octant {
+  long double c[kRootRes / 8 + 1], s[kRootRes / 8 + 1];
+};
+const Octant& octant() {
+  static const Octant* t = [] {
+    Octant* o = new Octant;
+    for (int64_t r = 0; r <= kRootRes / 8; ++r) {
+      const long double th = 2.0L * kPiL * (long double)r / (long double)kRootRes;
+      o->c[r] = r == 0 ? 1.0L : cosl(th);
+      o->s[r] = r == 0 ? 0.0L : sinl(th);
+    }
+    return o;
+  }();
+  return *t;
+}
+
+// the root exp(-2 pi i m / N) rounded to doubles; *base = its first-octant
+// index at kRootRes resolution (its rounding error is that entry's), or -1
+// when it is exact or was evaluated directly
+void unit_root_base(int64_t m, int64_t N, double* re, double* im, int64_t* base) {
   m %= N;
   if (m < 0) m += N;
+  *base = -1;
   long double c, s;               // cos, sin of 2 pi m / N
   if (N < 8) {
-    const long double th = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)N;
+    const long double th = 2.0L * kPiL * (long double)m / (long double)N;
     c = cosl(th);
     s = sinl(th);
     if (2 * m == N) { c = -1.0L; s = 0.0L; }
@@ -27,9 +58,18 @@ void unit_root(int64_t m, int64_t N, double* re, double* im) {
     int64_t r = m - quad * q4;            // 0 <= r < N/4
     bool swap = false;
     if (r > q8) { r = q4 - r; swap = true; }
-    const long double th = 2.0L * 3.141592653589793238462643383279502884L * (long double)r / (long double)N;
-    long double cb = cosl(th), sb = sinl(th);
-    if (r == 0) { cb = 1.0L; sb = 0.0L; }
+    long double cb, sb;
+    if (kRootRes % N == 0) {
+      const int64_t rr = r * (kRootRes / N);
+      cb = octant().c[rr];
+      sb = octant().s[rr];
+      if (rr != 0) *base = rr;
+    } else {
+      const long double th = 2.0L * kPiL * (long double)r / (long double)N;
+      cb = cosl(th);
+      sb = sinl(th);
+      if (r == 0) { cb = 1.0L; sb = 0.0L; }
+    }
     if (swap) { const long double t = cb; cb = sb; sb = t; }
     // angle = quad * pi/2 + phi, (cb, sb) = (cos phi, sin phi)
     switch (quad) {
@@ -42,21 +82,35 @@ void unit_root(int64_t m, int64_t N, double* re, double* im) {
   *re = (double)c;
   *im = (double)(-s);
 }
+}  // namespace
+
+void unit_root(int64_t m, int64_t N, double* re, double* im) {
+  int64_t base;
+  unit_root_base(m, N, re, im, &base);
+}
 
 double gen_fft_tables(double* tw, double* rtw) {
+  // worst rounding error of the roots: per first-octant entry (the other
+  // entries are exact sign changes and swaps of it), over the entries used
   long double worst = 0.0L;
-  auto track = [&](int64_t m, int64_t N, double re, double im) {
-    const long double th = 2.0L * 3.141592653589793238462643383279502884L * (long double)(m % N) / (long double)N;
-    const long double dr = (long double)re - cosl(th), di = (long double)im + sinl(th);
-    const long double e = sqrtl(dr * dr + di * di);
-    if (e > worst) worst = e;
+  std::vector<char> used(kRootRes / 8 + 1, 0);
+  auto root = [&](int64_t m, int64_t N, double* re, double* im) {
+    int64_t base;
+    unit_root_base(m, N, re, im, &base);
+    if (base >= 0) {
+      used[base] = 1;
+    } else {
+      const long double th = 2.0L * kPiL * (long double)(m % N) / (long double)N;
+      const long double dr = (long double)*re - cosl(th), di = (long double)*im + sinl(th);
+      const long double e = sqrtl(dr * dr + di * di);
+      if (e > worst) worst = e;
+    }
   };
   for (int k = 0; k < kRealTwN / 2 + 1; ++k) {
     double re, im;
-    unit_root(k, kRealTwN, &re, &im);
+    root(k, kRealTwN, &re, &im);
     rtw[2 * k] = re;
     rtw[2 * k + 1] = im;
-    track(k, kRealTwN, re, im);
   }
   for (int a = 1; a <= 4; ++a)
     for (int b = 0; b < kTwSpans; ++b) {
@@ -65,11 +119,17 @@ double gen_fft_tables(double* tw, double* rtw) {
       for (int k = 0; k < Ns; ++k)
         for (int r = 1; r < R; ++r) {
           double re, im;
-          unit_root((int64_t)r * k, (int64_t)R * Ns, &re, &im);
+          root((int64_t)r * k, (int64_t)R * Ns, &re, &im);
           t[2 * ((r - 1) * Ns + k)] = re;
           t[2 * ((r - 1) * Ns + k) + 1] = im;
-          track((int64_t)r * k, (int64_t)R * Ns, re, im);
         }
+    }
+  for (int64_t r = 0; r <= kRootRes / 8; ++r)
+    if (used[r]) {
+      const long double dc = (long double)(double)octant().c[r] - octant().c[r];
+      const long double ds = (long double)(double)octant().s[r] - octant().s[r];
+      const long double e = sqrtl(dc * dc + ds * ds);
+      if (e > worst) worst = e;
     }
   // constants of the radix-8/16 kernels: cos(pi/8), sin(pi/8), cos(pi/4)
   {
