@@ -186,11 +186,20 @@ void gen_ntt_tables(uint64_t* tw, uint64_t* r16, uint64_t* split) {
       const uint64_t w = gold_root((int64_t)R * Ns), wi = gold_inv(w);
       uint64_t* f = tw + ntt_tw_offset(R, Ns);
       uint64_t* g = tw + kNttTwEntries + ntt_tw_offset(R, Ns);
-      for (int k = 0; k < Ns; ++k)
+      // w^k and w^(-k) step by one multiplication per k, their r-th powers
+      // by one per r (exact modular arithmetic: the same values as powering)
+      uint64_t wk = 1, wik = 1;
+      for (int k = 0; k < Ns; ++k) {
+        uint64_t pf = wk, pg = wik;
         for (int r = 1; r < R; ++r) {
-          f[k * (R - 1) + (r - 1)] = gold_pow(w, (uint64_t)r * k);
-          g[k * (R - 1) + (r - 1)] = gold_pow(wi, (uint64_t)r * k);
+          f[k * (R - 1) + (r - 1)] = pf;
+          g[k * (R - 1) + (r - 1)] = pg;
+          pf = gold_mul(pf, wk);
+          pg = gold_mul(pg, wik);
         }
+        wk = gold_mul(wk, w);
+        wik = gold_mul(wik, wi);
+      }
     }
   const uint64_t w16 = gold_root(16), w16i = gold_inv(w16);
   for (int m = 0; m < 16; ++m) {
