@@ -50,9 +50,9 @@ __device__ __forceinline__ void row_status_publish(RowStatus* rs, double err, in
     unsigned long long bits = rs->err[0];
 #pragma unroll
     for (int k = 1; k < 16; ++k) bits = rs->err[k] > bits ? rs->err[k] : bits;
+    // a non-returning atomic: the work-group does not wait for it
     unsigned long long* dst = reinterpret_cast<unsigned long long*>(&st->max_err_bits);
-    if (bits > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMax(dst, bits);
+    if (bits) atomicMax(dst, bits);
     if (bad) status_or(st, ST_BOUND);
   }
 }
@@ -438,27 +438,28 @@ __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, i
     if (b >= ncw) return (uint64_t)(top >> (b - ncw < 63 ? b - ncw : 63));
     const int e = b / w;
     const int off = b - e * w;
+    // only the low 64 bits are kept, and every shift is below 64
     if (w < 8) {                                    // more limbs per word than the window
-      unsigned __int128 acc = (unsigned __int128)((uint64_t)coef[e] >> off);
+      uint64_t acc = (uint64_t)coef[e] >> off;
       int nb = w - off, k = e + 1;
-      for (; nb < 64 && k < NC; ++k, nb += w) acc |= (unsigned __int128)(uint64_t)coef[k] << nb;
-      if (nb < 64) acc |= (unsigned __int128)(uint64_t)top << nb;
-      return (uint64_t)acc;
+      for (; nb < 64 && k < NC; ++k, nb += w) acc |= (uint64_t)coef[k] << nb;
+      if (nb < 64) acc |= (uint64_t)top << nb;
+      return acc;
     }
     int64_t l[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) l[j] = coef[e + j < NC ? e + j : NC - 1];
-    unsigned __int128 acc = (unsigned __int128)((uint64_t)l[0] >> off);
+    uint64_t acc = (uint64_t)l[0] >> off;
     int nb = w - off;
 #pragma unroll
     for (int j = 1; j < 10; ++j) {
       if (nb < 64) {
         const uint64_t v = e + j < NC ? (uint64_t)l[j] : (uint64_t)top;
-        acc |= (unsigned __int128)v << nb;
+        acc |= v << nb;
         nb = e + j < NC ? nb + w : 64;
       }
     }
-    return (uint64_t)acc;
+    return acc;
   };
   // floor words go straight out; with a round-up increment the words below
   // the first one that is not all ones become 0 and that one gains 1
