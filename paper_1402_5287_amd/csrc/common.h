@@ -44,7 +44,15 @@ __device__ inline void row_status_init(RowStatus* rs) {
 }
 // every thread; ends with a barrier
 __device__ __forceinline__ void row_status_publish(RowStatus* rs, double err, int bad, DevStatus* st) {
-  atomicMax(&rs->err[threadIdx.x & 15], (unsigned long long)__double_as_longlong(err));
+  // a maximum per wavefront first (err >= 0, so its bits order as unsigned),
+  // then one LDS atomic per wave
+  unsigned long long eb = (unsigned long long)__double_as_longlong(err);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long q = (unsigned long long)__shfl_xor((long long)eb, o, 64);
+    eb = q > eb ? q : eb;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(&rs->err[(threadIdx.x >> 6) & 15], eb);
   bad = __syncthreads_or(bad);
   if (threadIdx.x == 0 && st) {
     unsigned long long bits = rs->err[0];
@@ -469,7 +477,15 @@ __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, i
     y[m] = um;
     if (um != ~0ull && m < firstme) firstme = m;
   }
-  if (up && firstme < W) atomicMin(&red[31], (uint32_t)firstme);
+  // the first word that is not all ones: a minimum per wavefront first, then
+  // one LDS atomic per wave (every thread on one address serialises); up is
+  // uniform over the block
+  if (up) {
+    int fm = firstme;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) fm = min(fm, __shfl_xor(fm, o, 64));
+    if ((t & 63) == 0 && fm < W) atomicMin(&red[31], (uint32_t)fm);
+  }
   __syncthreads();
   if (up) {
     const int first = (int)red[31];
