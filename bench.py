@@ -61,11 +61,13 @@ KERNEL_NAMES = {"split_fft": ("k_rows_fwd", "k_cols_pass", "k_rows_inv"),
 def kernel_bytes(algo, n, W, info):
     """Algorithmic HBM bytes of the three kernels of one planned matvec:
     x words in + X1 spectrum out; X1 in + resident spectrum of h in + Y1 out;
-    Y1 in + y words out.  split_fft keeps the Hermitian half (Nz/2 + 1
-    complex binary64 per row), ntt the full Nz residues (8 bytes each)."""
+    Y1 in + y words out.  split_fft keeps the Hermitian half (spectrum_cols
+    complex binary64 per row: Nz/2 when its two real bins share a column,
+    else Nz/2 + 1; the resident spectrum has Nz/2 + 1 columns of Nt), ntt the
+    full Nz residues (8 bytes each)."""
     Nt, Nz = info["Nt"], info["Nz"]
-    row = (Nz // 2 + 1) * 16 if algo == "split_fft" else Nz * 8
-    cols = row
+    row = info["spectrum_cols"] * 16 if algo == "split_fft" else Nz * 8
+    cols = (Nz // 2 + 1) * 16 if algo == "split_fft" else row
     return (n * W * 8 + n * row, 2 * n * row + Nt * cols, n * row + n * W * 8)
 
 

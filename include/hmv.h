@@ -113,6 +113,11 @@ typedef struct {
   int64_t matvec_workspace_bytes;
   int32_t cols_variant;   /* split-FFT launch variants (see hmv_autotune)        */
   int32_t rows_inv_variant;
+  int32_t spectrum_cols;  /* split-FFT: limb-frequency columns of the spectra of
+                             x and y, Nz/2 when the two real limb bins share one
+                             column (the error bound allows it), else Nz/2 + 1;
+                             0 for the other paths                             */
+  int32_t reserved;
 } hmv_plan_info_t;
 
 int64_t hmv_plan_bytes(int kind, int64_t n, int32_t P, int algo);
@@ -221,6 +226,12 @@ int hmv_debug_force_width(int32_t w);
  * values of hmv_plan_info_t; a variant that does not exist for the shape
  * falls back to variant 0 of that bit); -1, -1 restores tuning.            */
 int hmv_debug_force_variants(int32_t cols_variant, int32_t rows_inv_variant);
+/* tests only: spectrum layout of later split-FFT plans.  z3 = 0 keeps the
+ * limb transforms at powers of two (1 or -1: 3 * 2^k points where smaller);
+ * pack = 0 or 1 fixes whether the two real limb bins share one column (-1:
+ * packed where the error bound allows it).  The bound is still enforced.
+ * Returns HMV_EINVAL for values outside -1..1.                             */
+int hmv_debug_force_layout(int32_t z3, int32_t pack);
 /* tests only: spin limit of the dependency waits of the single-launch batch
  * driver (switched off in this build; kept for its test); 0 = default.     */
 int hmv_debug_batch_spin_limit(int32_t spins);

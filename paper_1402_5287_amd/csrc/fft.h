@@ -31,10 +31,22 @@ __device__ __align__(4096) double2 g_rtw[kRealTwEntries];
 // common even strides read consecutive entries
 __device__ __align__(4096) double2 g_rtw2[kRealTwEntries2];
 
+// exp(-2 pi i s / (3 kR3MaxK)), s < kR3MaxK
+__device__ __align__(4096) double2 g_r3tw[kR3Entries];
+
 // exp(-2 pi i k rs / kRealTwN)
 __device__ __forceinline__ double2 real_root(int k, int rs) {
   return (rs & 1) ? g_rtw[k * rs] : g_rtw2[k * (rs >> 1)];
 }
+
+// exp(-2 pi i s / 3K), K = 2^LOGK, s < K
+template <int LOGK>
+__device__ __forceinline__ double2 r3_root(int s) {
+  return g_r3tw[s << (kR3MaxLogK - LOGK)];
+}
+// sqrt(3)/2 and sqrt(3), correctly rounded
+constexpr double kSqrt3h = 0.86602540378443864676;
+constexpr double kSqrt3 = 1.73205080756887729353;
 
 // ---------------------------------------------------------------- complex ops
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -222,6 +234,89 @@ __device__ __forceinline__ void fft_lds_t(double2* buf, int sign) {
   if constexpr (REM == 1) stockham_pass<2, 8>(buf, N, Ns, sign);
   else if constexpr (REM == 2) stockham_pass<4, 4>(buf, N, Ns, sign);
   else if constexpr (REM == 3) stockham_pass<8, 2>(buf, N, Ns, sign);
+}
+
+// ------------------------------------------------------------------------
+// Two independent transforms in one work-group, of NA = 2^LA points in bufA
+// and NB = 2^LB points in bufB (each with its own lds_slot layout), run pass
+// by pass together: pass p has span 16^p in both, radix 16 while four or more
+// bits remain, then the tail radix, and radix 1 (no work) once a transform
+// is done.  The butterflies of A come first in one index space, then those of
+// B; thread t takes indices t, t + T, ...  T = blockDim.x.
+
+template <int R, int N>
+__device__ __forceinline__ void pair_read(const double2* buf, int b, int Ns, int sign,
+                                          double2* v) {
+  constexpr int nbf = N / R;
+  const int k = b & (Ns - 1);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    v[r] = buf[(nbf & 15) == 0 ? lds_step(lds_slot(b), r, nbf) : lds_slot(b + r * nbf)];
+  if (Ns > 1) {
+    const double2* tw = g_tw + tw_offset(R, Ns);
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      double2 w = tw[(r - 1) * Ns + k];
+      if (sign > 0) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void pair_write(double2* buf, int b, int Ns, int sign, double2* v) {
+  const int k = b & (Ns - 1);
+  dft<R>(v, sign);
+  const int base = (b - k) * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    buf[(Ns & 15) == 0 ? lds_step(lds_slot(base), r, Ns) : lds_slot(base + r * Ns)] = v[r];
+}
+
+template <int RA, int RB, int NA, int NB, int T>
+__device__ __forceinline__ void stockham_pass_pair(double2* bufA, double2* bufB, int Ns,
+                                                   int sign) {
+  constexpr int nbA = RA > 1 ? NA / RA : 0, nbB = RB > 1 ? NB / RB : 0;
+  constexpr int IT = (nbA + nbB + T - 1) / T;
+  constexpr int RM = RA > RB ? RA : RB;
+  const int t = threadIdx.x;
+  double2 v[IT][RM];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int u = t + i * T;
+    if constexpr (nbA > 0) {
+      if (u < nbA) pair_read<RA, NA>(bufA, u, Ns, sign, v[i]);
+    }
+    if constexpr (nbB > 0) {
+      if (u >= nbA && u < nbA + nbB) pair_read<RB, NB>(bufB, u - nbA, Ns, sign, v[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int u = t + i * T;
+    if constexpr (nbA > 0) {
+      if (u < nbA) pair_write<RA>(bufA, u, Ns, sign, v[i]);
+    }
+    if constexpr (nbB > 0) {
+      if (u >= nbA && u < nbA + nbB) pair_write<RB>(bufB, u - nbA, Ns, sign, v[i]);
+    }
+  }
+  __syncthreads();
+}
+
+// radix of pass p of a 2^LG-point transform (1 once it is done)
+__host__ __device__ constexpr int pass_radix(int LG, int p) {
+  return p < LG / 4 ? 16 : (p == LG / 4 && (LG & 3)) ? (1 << (LG & 3)) : 1;
+}
+
+template <int LA, int LB, int T, int p = 0>
+__device__ __forceinline__ void fft_pair_lds(double2* bufA, double2* bufB, int sign) {
+  constexpr int RA = pass_radix(LA, p), RB = pass_radix(LB, p);
+  if constexpr (RA > 1 || RB > 1) {
+    stockham_pass_pair<RA, RB, (1 << LA), (1 << LB), T>(bufA, bufB, 1 << (4 * p), sign);
+    fft_pair_lds<LA, LB, T, p + 1>(bufA, bufB, sign);
+  }
 }
 
 // ------------------------------------------------------------------------

@@ -30,4 +30,10 @@ constexpr int64_t kTwEntries = (1 + 3 + 7 + 15) * (1 + 8 + 16 + 64 + 256 + 512 +
 constexpr int kRealTwN = 16384;
 constexpr int64_t kRealTwEntries = kRealTwN / 2 + 1;
 constexpr int64_t kRealTwEntries2 = kRealTwN / 4 + 1;
+// radix-3 step of the limb transforms of 3K points (K a power of two, at most
+// kR3MaxK): exp(-2 pi i s / (3 kR3MaxK)), s < kR3MaxK; a transform of 3K
+// points reads every (kR3MaxK / K)-th entry
+constexpr int kR3MaxLogK = 11;
+constexpr int kR3MaxK = 1 << kR3MaxLogK;
+constexpr int64_t kR3Entries = kR3MaxK;
 }  // namespace hmv

@@ -34,13 +34,14 @@ namespace {
 std::mutex g_tab_mu;
 bool g_tab_ready[64] = {};
 double g_beta = -1.0;
-std::vector<double> g_tw_host, g_rtw_host, g_rtw2_host;
+std::vector<double> g_tw_host, g_rtw_host, g_rtw2_host, g_r3_host;
 
 void ensure_host_tables() {
   if (g_beta < 0.0) {
     g_tw_host.assign(2 * kTwEntries, 0.0);
     g_rtw_host.assign(2 * kRealTwEntries, 0.0);
-    g_beta = gen_fft_tables(g_tw_host.data(), g_rtw_host.data());
+    g_r3_host.assign(2 * kR3Entries, 0.0);
+    g_beta = gen_fft_tables(g_tw_host.data(), g_rtw_host.data(), g_r3_host.data());
     g_rtw2_host.assign(2 * kRealTwEntries2, 0.0);
     for (int64_t k = 0; k < kRealTwEntries2; ++k) {
       g_rtw2_host[2 * k] = g_rtw_host[4 * k];
@@ -70,6 +71,8 @@ hipError_t fft_tables_init() {
   if (e != hipSuccess) return e;
   e = hipMemcpyToSymbol(HIP_SYMBOL(g_rtw2), g_rtw2_host.data(),
                         sizeof(double) * g_rtw2_host.size());
+  if (e != hipSuccess) return e;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(g_r3tw), g_r3_host.data(), sizeof(double) * g_r3_host.size());
   if (e != hipSuccess) return e;
   g_tab_ready[dev] = true;
   return hipSuccess;
@@ -147,7 +150,9 @@ __global__ void __launch_bounds__(256) k_h_norms(const uint64_t* __restrict__ h,
 // stored to row r of the tiled spectrum.  A thread's root loads are issued
 // eight at a time so that they are in flight together.
 // Stored in tiles of TW bins (tidx).
-template <int TW>
+// PACK0: bins 0 and M, both real, share column 0 as X[0] + i X[M] (columns
+// 0 .. M-1 are written); otherwise bins 0 .. M go to columns 0 .. M.
+template <int TW, bool PACK0 = false>
 __device__ inline void pack_real_row(const double2* buf, int M, double2* __restrict__ out, int r,
                                      int rows_alloc) {
   const int T = blockDim.x, t = threadIdx.x;
@@ -167,7 +172,13 @@ __device__ inline void pack_real_row(const double2* buf, int M, double2* __restr
         const double2 A = cadd(zk, conj2(zm)), B = csub(zk, conj2(zm));
         const double2 Q = cmul(wv[u], B);
         const int64_t o = tidx<TW>(k, r, rows_alloc);
-        out[o] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
+        if constexpr (PACK0) {
+          // X[0] = Z[0].re + Z[0].im, X[M] = Z[0].re - Z[0].im
+          if (k == 0) out[o] = make_double2(zk.x + zk.y, zk.x - zk.y);
+          else if (k < M) out[o] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
+        } else {
+          out[o] = make_double2(0.5 * (A.x + Q.y), 0.5 * (A.y - Q.x));
+        }
       }
     }
   }
@@ -179,7 +190,7 @@ template <int LOGM>
 __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict__ in, int W, int P,
                                                      int w, int L, int count, int gather_n,
                                                      double2* __restrict__ out, int rows_alloc,
-                                                     DevStatus* st) {
+                                                     int pack, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint64_t wd[kMaxWords];
   __shared__ uint32_t red[32];
@@ -206,7 +217,8 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds_t<LOGM>(buf, -1);
-  pack_real_row<kX1Tile>(buf, M, out, r, rows_alloc);
+  if (pack) pack_real_row<kX1Tile, true>(buf, M, out, r, rows_alloc);
+  else pack_real_row<kX1Tile, false>(buf, M, out, r, rows_alloc);
 }
 
 // The index-axis transforms of N_t = 2 Nh points are split by one radix-2
@@ -220,12 +232,28 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
 // decimation-in-time step).  Each half needs Nh points of LDS, so the
 // headline shape (N_t = 8192) runs two work-groups per CU.
 
+// Column 0 of the row spectra packs the two real bins of the limb axis (bin 0
+// and the last bin of the Hermitian half), c = a + i b with a, b real
+// columns.  Its index-axis transform U = A + i B gives the two spectra back
+// through the partner bin U*[k] = conj U[N_t - k]:
+//   A = (U + U*) / 2,   i B = (U - U*) / 2,
+// and the product the matvec needs, A Ha + i (B Hb), keeps its two parts
+// apart (the inverse of each is real):
+//   V = (U + U*) Ha' + (U - U*) Hb',   Ha' = Ha / 2,  Hb' = Hb / 2,
+// with Ha' in the resident column 0 and Hb' in the extra column C.  Partner
+// bins inside the even / odd halves: k <-> (Nh - k) mod Nh (even),
+// k <-> Nh - 1 - k (odd).  The real bins of the power-of-two form and of the
+// 3K form are both packed this way when the plan's error bound allows it
+// (pack = 1): a spectrum then has N_z / 2 columns, otherwise N_z / 2 + 1.
+
 // Column pass of the plan: transform each limb-frequency column of h over the
-// index axis and store it scaled by 2^-(log N_t + log N_z) (exact), so the
-// matvec's unnormalised inverse transforms need no further scaling.
+// index axis and store it scaled by 1 / (N_t N_z) (exact for a power-of-two
+// N_z, one rounding of 1/3 otherwise), so the matvec's unnormalised inverse
+// transforms need no further scaling.  Packed: column 0 stores Ha' and Hb'
+// (above).
 template <int LOGNH>
 __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H1, int rows,
-                                                   int C, double scale,
+                                                   int C, double scale, int pack,
                                                    double2* __restrict__ Hh) {
   extern __shared__ double2 buf[];
   const int c = xcd_slot(blockIdx.x, gridDim.x);
@@ -255,12 +283,62 @@ __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H
     }
     fft_regs<LOGNH>(v, buf, -1);
     double2* dst = half == 0 ? he : ho;
-    if (act) {
+    if (pack && c == 0) {
+      // Ha = (Hc + Hc*) / 2, Hb = -i (Hc - Hc*) / 2; stored halved and scaled
+      if (act) {
+#pragma unroll
+        for (int j = 0; j < per; ++j) buf[lds_slot(t + Ta * j)] = v[j];
+      }
+      __syncthreads();
+      double2* dstb = Hh + (int64_t)C * (2 * Nh) + (half == 0 ? 0 : Nh);
+      const double q = 0.25 * scale;
+      if (act) {
+#pragma unroll
+        for (int j = 0; j < per; ++j) {
+          const int k = t + Ta * j;
+          const int kp = half == 0 ? (Nh - k) & (Nh - 1) : Nh - 1 - k;
+          const double2 pc = conj2(buf[lds_slot(kp)]);
+          const double2 sa = cadd(v[j], pc), sb = csub(v[j], pc);
+          dst[k] = make_double2(sa.x * q, sa.y * q);
+          dstb[k] = make_double2(sb.y * q, -sb.x * q);
+        }
+      }
+      __syncthreads();
+    } else if (act) {
 #pragma unroll
       for (int j = 0; j < per; ++j)
         dst[t + Ta * j] = make_double2(v[j].x * scale, v[j].y * scale);
     }
   }
+}
+
+// The product of the packed column 0 in one half (odd = 0 even bins, 1 odd
+// bins): v[j] = (U + U*) Ha' + (U - U*) Hb' at bin k = t + Ta j, the partner
+// bins exchanged through LDS.  Every thread of the block calls it.
+template <int R>
+__device__ __forceinline__ void packed_product(double2* v, double2* buf, const double2* ha,
+                                               const double2* hb, int Nh, int odd, int Ta,
+                                               int per) {
+  const int t = threadIdx.x;
+  const bool act = t < Ta;
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (j < per) buf[lds_slot(t + Ta * j)] = v[j];
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      if (j < per) {
+        const int k = t + Ta * j;
+        const int kp = odd ? Nh - 1 - k : (Nh - k) & (Nh - 1);
+        const double2 pc = conj2(buf[lds_slot(kp)]);
+        v[j] = cadd(cmul(cadd(v[j], pc), ha[k]), cmul(csub(v[j], pc), hb[k]));
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // Column pass of the matvec: x column reversed (x_hat[s] = x[n-1-s], zero for
@@ -274,7 +352,7 @@ __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H
 template <int LOGNH, int R>
 __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
     const double2* __restrict__ X1, const double2* __restrict__ Hh, int n, int C, int linear,
-    double2* __restrict__ Y1) {
+    int pack, double2* __restrict__ Y1) {
   extern __shared__ double2 buf[];
   const int c = linear ? (int)blockIdx.x : xcd_slot(blockIdx.x, gridDim.x);
   if (c >= C) return;
@@ -304,7 +382,9 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
   }
   // even frequencies
   fft_regs_r<LOGNH, R>(v, buf, -1);
-  if (act) {
+  if (pack && c == 0) {
+    packed_product<R>(v, buf, he, Hh + (int64_t)C * (2 * Nh), Nh, 0, Ta, per);
+  } else if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) v[j] = cmul(v[j], he[t + Ta * j]);
   }
@@ -322,7 +402,9 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
     }
   }
   fft_regs_r<LOGNH, R>(o, buf, -1);
-  if (act) {
+  if (pack && c == 0) {
+    packed_product<R>(o, buf, ho, Hh + (int64_t)C * (2 * Nh) + Nh, Nh, 1, Ta, per);
+  } else if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) o[j] = cmul(o[j], ho[t + Ta * j]);
   }
@@ -350,11 +432,11 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
 template <int LOGM, int R>
 __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
     const double2* __restrict__ Y1, int n, int L, int w, int P, int W, int out_reverse,
-    int carry_off, uint64_t* __restrict__ y, DevStatus* st) {
+    int carry_off, int pack, uint64_t* __restrict__ y, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint32_t red[32];
   __shared__ RowStatus rst;
-  __shared__ double2 ytop;                 // Y[M]
+  __shared__ double2 ytop;                 // Y[M] (packed: the imaginary part of column 0)
   // rows grouped per XCD: consecutive rows share the lines of a Y1 tile
   const int i = xcd_slot(blockIdx.x, gridDim.x);
   if (i >= n) return;
@@ -367,7 +449,6 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
   // the row and the packing roots, all loads in flight together (one
   // guarded block; element k = t + Ta j covers every k < M)
   double2 wk[R], v[R];
-  const double2 top = Y1[tidx<kY1Tile>(M, i, n)];
   if (act) {
 #pragma unroll
     for (int j = 0; j < per; ++j) {
@@ -375,10 +456,19 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
       v[j] = Y1[tidx<kY1Tile>(k, i, n)];
       wk[j] = conj2(real_root(k, rs));
     }
+    // packed: column 0 holds Y[0] + i Y[M] (both real); otherwise Y[M] is
+    // column M
+    if (t == 0) {
+      if (pack) {
+        ytop = make_double2(v[0].y, 0.0);
+        v[0] = make_double2(v[0].x, 0.0);
+      } else {
+        ytop = Y1[tidx<kY1Tile>(M, i, n)];
+      }
+    }
 #pragma unroll
     for (int j = 0; j < per; ++j) buf[lds_slot(t + Ta * j)] = v[j];
   }
-  if (t == 0) ytop = top;
   __syncthreads();
   // Z[k] = (Y[k] + conj Y[M-k]) + i w^-k (Y[k] - conj Y[M-k]),  k < M
   if (act) {
@@ -413,6 +503,193 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
       if (2 * m < NC) *reinterpret_cast<longlong2*>(coef + 2 * m) = make_longlong2(i0, i1);
       else if (i0 != 0) bad = 1;
       if (2 * m + 1 >= NC && i1 != 0) bad = 1;
+    }
+  }
+  row_status_publish(&rst, maxerr, bad, st);
+  int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
+  const int row = out_reverse ? (n - 1 - i) : i;
+  carry_round_pack_fit(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
+}
+
+// ------------------------------------------------------------------ 3K-point limb transforms
+// Limb transforms of N_z = 3K real points (K = 2^LOGK) where 3K is the
+// smallest admissible size (2L - 1 <= 3K < 2^ceil(log2(2L - 1))).  One
+// radix-3 decimation-in-frequency step splits the transform of x (x[e] = 0
+// for e >= L) into two K-point transforms, with w = exp(-2 pi i / 3K) and
+// r = exp(-2 pi i / 3):
+//   bin 3m   = sum_s w^(3ms) u0[s],  u0[s] = x[s] + x[s+K] + x[s+2K]      (real)
+//   bin 3m+1 = sum_s w^(3ms) u1[s],  u1[s] = w^s (x[s] + r x[s+K] + r^2 x[s+2K])
+// and bin 3m+2 = conj(bin 3(K-1-m)+1) for real x.  A row stores the K/2 + 1
+// bins 3m (m <= K/2, the Hermitian half of the real K-point transform; the
+// real bins 0 and 3(K/2) share column 0) in columns 0 .. K/2-1 and the K bins
+// 3m+1 in columns K/2 .. 3K/2-1: N_z/2 columns, as for a power-of-two N_z.
+// Each limb frequency is one column of the 2-D transform.
+// The inverse, with z0, z1 the unnormalised inverse K-point transforms of the
+// bins 3m and 3m+1 and v[s] = w^-s z1[s]:
+//   N_z x[s + jK] = z0[s] + 2 Re(r^-j v[s]),   j = 0, 1, 2
+// i.e. z0 + 2 v.re,  z0 - v.re - sqrt3 v.im,  z0 - v.re + sqrt3 v.im.
+// The real K-point transform runs as a K/2-point complex one plus the packing
+// step; the K/2- and K-point transforms run together (fft_pair_lds).
+__host__ __device__ constexpr int rows3_threads(int K) { return K / 8 < 64 ? 64 : K / 8; }
+
+template <int LOGK>
+__global__ void __launch_bounds__(256) k_rows_fwd3(const uint64_t* __restrict__ in, int W, int P,
+                                                   int w, int L, int count, int gather_n,
+                                                   double2* __restrict__ out, int rows_alloc,
+                                                   int pack, DevStatus* st) {
+  extern __shared__ double2 buf[];
+  __shared__ uint32_t red[32];
+  const int r = xcd_slot(blockIdx.x, gridDim.x);
+  if (r >= count) return;
+  constexpr int K = 1 << LOGK, KA = K / 2, T = rows3_threads(K), S = K / T;
+  const int t = threadIdx.x;
+  // the L digits (digit e in double 2 lds_slot(e/2) + e%2, the padded
+  // layout), then the W words, share the transform buffer (L <= (3K+1)/2 and
+  // W < L / 3 + 2: at most about 17 K of its 25.5 K bytes), which keeps the
+  // work-group's LDS small enough for three per CU
+  double* dig = reinterpret_cast<double*>(buf);
+  uint64_t* wd = reinterpret_cast<uint64_t*>(buf + lds_points((L + 1) / 2));
+  double2* bufA = buf;                              // K/2 points
+  double2* bufB = buf + lds_points(KA);             // K points
+  load_words(in + (int64_t)gather_row(r, gather_n) * W, W, wd);
+  __syncthreads();
+  if (t < 64) {
+    const bool ok = number_in_range_wave(wd, W, P);
+    if (!ok && t == 0) status_or(st, ST_RANGE);
+  }
+  split_balanced(wd, W, w, L, [&](int e, int d) { dig[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; },
+                 red);
+  __syncthreads();
+  // radix-3 step: u0 exact (digit sums), u1 with one constant and one
+  // tabulated root
+  double u0[S];
+  double2 u1[S];
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const int s = t + T * j;
+    auto digit = [&](int e) { return e < L ? dig[2 * lds_slot(e >> 1) + (e & 1)] : 0.0; };
+    const double a = digit(s), b = digit(s + K), c = digit(s + 2 * K);
+    u0[j] = a + b + c;
+    u1[j] = cmul(make_double2(a - 0.5 * (b + c), kSqrt3h * (c - b)), r3_root<LOGK>(s));
+  }
+  __syncthreads();
+  double* bdA = reinterpret_cast<double*>(bufA);
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const int s = t + T * j;
+    bdA[2 * lds_slot(s >> 1) + (s & 1)] = u0[j];
+    bufB[lds_slot(s)] = u1[j];
+  }
+  __syncthreads();
+  fft_pair_lds<LOGK - 1, LOGK, T>(bufA, bufB, -1);
+  if (pack) pack_real_row<kX1Tile, true>(bufA, KA, out, r, rows_alloc);
+  else pack_real_row<kX1Tile, false>(bufA, KA, out, r, rows_alloc);
+  const int b0 = pack ? KA : KA + 1;           // first column of the bins 3m+1
+  for (int m = t; m < K; m += T) out[tidx<kX1Tile>(b0 + m, r, rows_alloc)] = bufB[lds_slot(m)];
+}
+
+template <int LOGK>
+__global__ void __launch_bounds__(256) k_rows_inv3(const double2* __restrict__ Y1, int n, int L,
+                                                   int w, int P, int W, int out_reverse,
+                                                   int carry_off, int pack,
+                                                   uint64_t* __restrict__ y, DevStatus* st) {
+  extern __shared__ double2 buf[];
+  __shared__ uint32_t red[32];
+  __shared__ RowStatus rst;
+  __shared__ double2 ytop;                 // bin 3(K/2) (packed: the imaginary part of column 0)
+  const int i = xcd_slot(blockIdx.x, gridDim.x);
+  if (i >= n) return;
+  row_status_init(&rst);
+  constexpr int K = 1 << LOGK, KA = K / 2, T = rows3_threads(K), S = K / T;
+  constexpr int SA = KA >= T ? KA / T : 1;
+  constexpr int rs = kRealTwN / K;         // packing roots of order K
+  const int t = threadIdx.x;
+  double2* bufA = buf;
+  double2* bufB = buf + lds_points(KA);
+  // the row: bins 3m in columns 0 .. K/2-1 (packed: column 0 = bin 0 + i
+  // bin 3(K/2); otherwise bin 3(K/2) in column K/2), then the bins 3m+1, all
+  // loads in flight together
+  {
+    const int b0 = pack ? KA : KA + 1;
+    double2 va[SA], vb[S];
+#pragma unroll
+    for (int j = 0; j < SA; ++j) {
+      const int k = t + T * j;
+      va[j] = Y1[tidx<kY1Tile>(k < KA ? k : 0, i, n)];
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) vb[j] = Y1[tidx<kY1Tile>(b0 + t + T * j, i, n)];
+    if (t == 0) {
+      if (pack) {
+        ytop = make_double2(va[0].y, 0.0);
+        va[0] = make_double2(va[0].x, 0.0);
+      } else {
+        ytop = Y1[tidx<kY1Tile>(KA, i, n)];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < SA; ++j) {
+      const int k = t + T * j;
+      if (k < KA) bufA[lds_slot(k)] = va[j];
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) bufB[lds_slot(t + T * j)] = vb[j];
+  }
+  __syncthreads();
+  // unpacking step of the real K-point inverse:
+  // Z[k] = (Y[k] + conj Y[K/2-k]) + i w_K^-k (Y[k] - conj Y[K/2-k]),  k < K/2
+  {
+    double2 za[SA];
+#pragma unroll
+    for (int j = 0; j < SA; ++j) {
+      const int k = t + T * j;
+      if (k < KA) {
+        const double2 yk = bufA[lds_slot(k)];
+        const double2 ym = k == 0 ? ytop : bufA[lds_slot(KA - k)];
+        const double2 E = cadd(yk, conj2(ym)), D = csub(yk, conj2(ym));
+        const double2 Q = cmul(D, conj2(real_root(k, rs)));
+        za[j] = make_double2(E.x - Q.y, E.y + Q.x);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SA; ++j) {
+      const int k = t + T * j;
+      if (k < KA) bufA[lds_slot(k)] = za[j];
+    }
+  }
+  __syncthreads();
+  fft_pair_lds<LOGK - 1, LOGK, T>(bufA, bufB, +1);
+  // recombine, round every coefficient to its integer
+  const int NC = 2 * L - 1;
+  const double* bdA = reinterpret_cast<const double*>(bufA);
+  int64_t iv[S][3];
+  double maxerr = 0.0;
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+    const int s = t + T * j;
+    const double z0 = bdA[2 * lds_slot(s >> 1) + (s & 1)];
+    const double2 v = cmul(bufB[lds_slot(s)], conj2(r3_root<LOGK>(s)));
+    const double c[3] = {z0 + 2.0 * v.x, (z0 - v.x) - kSqrt3 * v.y, (z0 - v.x) + kSqrt3 * v.y};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double rr;
+      iv[j][q] = round_to_int(c[q], &rr);
+      maxerr = fmax(maxerr, fabs(c[q] - rr));
+      // every true coefficient is below 2^50 in magnitude (plan constraint)
+      if (fabs(c[q]) >= kCoefLimit) bad = 1;
+    }
+  }
+  __syncthreads();
+  int64_t* coef = reinterpret_cast<int64_t*>(buf);
+#pragma unroll
+  for (int j = 0; j < S; ++j) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int e = t + T * j + q * K;
+      if (e < NC) coef[e] = iv[j][q];
+      else if (iv[j][q] != 0) bad = 1;
     }
   }
   row_status_publish(&rst, maxerr, bad, st);
@@ -462,7 +739,7 @@ hipError_t launch_h_norms(const uint64_t* h, int W, int P, int rows, int gather_
 
 template <int LOGM>
 hipError_t rows_fwd_t(const uint64_t* in, int W, int P, int w, int L, int count, int gather_n,
-                      double2* out, int rows_alloc, DevStatus* st, hipStream_t s) {
+                      double2* out, int rows_alloc, int pack, DevStatus* st, hipStream_t s) {
   constexpr int M = 1 << LOGM;
   const int T = fft_threads(M, 16);           // the LDS transform needs N/16 threads
   const size_t lds = sizeof(double2) * (size_t)lds_points(M);
@@ -470,16 +747,16 @@ hipError_t rows_fwd_t(const uint64_t* in, int W, int P, int w, int L, int count,
   if (e != hipSuccess) return e;
   const int grid = (count + 7) / 8 * 8;         // xcd_slot needs a multiple of 8
   hipLaunchKernelGGL(k_rows_fwd<LOGM>, dim3(grid), dim3(T), lds, s, in, W, P, w, L, count,
-                     gather_n, out, rows_alloc, st);
+                     gather_n, out, rows_alloc, pack, st);
   return hipGetLastError();
 }
 
 hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int count,
-                           int gather_n, int logM, double2* out, int rows_alloc, DevStatus* st,
-                           hipStream_t s) {
+                           int gather_n, int logM, double2* out, int rows_alloc, int pack,
+                           DevStatus* st, hipStream_t s) {
   switch (logM) {
 #define HMV_RF(k) \
-  case k: return rows_fwd_t<k>(in, W, P, w, L, count, gather_n, out, rows_alloc, st, s);
+  case k: return rows_fwd_t<k>(in, W, P, w, L, count, gather_n, out, rows_alloc, pack, st, s);
     HMV_RF(1) HMV_RF(2) HMV_RF(3) HMV_RF(4) HMV_RF(5) HMV_RF(6) HMV_RF(7) HMV_RF(8) HMV_RF(9)
     HMV_RF(10) HMV_RF(11) HMV_RF(12)
 #undef HMV_RF
@@ -487,40 +764,65 @@ hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int c
   }
 }
 
+template <int LOGK>
+hipError_t rows_fwd3_t(const uint64_t* in, int W, int P, int w, int L, int count, int gather_n,
+                       double2* out, int rows_alloc, int pack, DevStatus* st, hipStream_t s) {
+  constexpr int K = 1 << LOGK;
+  const size_t lds = sizeof(double2) * (size_t)(lds_points(K / 2) + lds_points(K));
+  hipError_t e = set_lds((const void*)k_rows_fwd3<LOGK>, lds);
+  if (e != hipSuccess) return e;
+  const int grid = (count + 7) / 8 * 8;         // xcd_slot needs a multiple of 8
+  hipLaunchKernelGGL(k_rows_fwd3<LOGK>, dim3(grid), dim3(rows3_threads(K)), lds, s, in, W, P, w,
+                     L, count, gather_n, out, rows_alloc, pack, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_fwd3(const uint64_t* in, int W, int P, int w, int L, int count,
+                            int gather_n, int logK, double2* out, int rows_alloc, int pack,
+                            DevStatus* st, hipStream_t s) {
+  switch (logK) {
+#define HMV_RF3(k) \
+  case k: return rows_fwd3_t<k>(in, W, P, w, L, count, gather_n, out, rows_alloc, pack, st, s);
+    HMV_RF3(6) HMV_RF3(7) HMV_RF3(8) HMV_RF3(9) HMV_RF3(10) HMV_RF3(11)
+#undef HMV_RF3
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int LOGNH>
-hipError_t cols_plan_t(const double2* H1, int rows, int C, double scale, double2* Hh,
+hipError_t cols_plan_t(const double2* H1, int rows, int C, double scale, int pack, double2* Hh,
                        hipStream_t s) {
   const size_t lds = sizeof(double2) * (size_t)lds_points(1 << LOGNH);
   hipError_t e = set_lds((const void*)k_cols_plan<LOGNH>, lds);
   if (e != hipSuccess) return e;
   const int grid = (C + 7) / 8 * 8;
   hipLaunchKernelGGL(k_cols_plan<LOGNH>, dim3(grid), dim3(fft_threads(1 << LOGNH, 16)), lds, s, H1,
-                     rows, C, scale, Hh);
+                     rows, C, scale, pack, Hh);
   return hipGetLastError();
 }
 
 template <int LOGNH, int R>
-hipError_t cols_pass_r(const double2* X1, const double2* Hh, int n, int C, int linear,
+hipError_t cols_pass_r(const double2* X1, const double2* Hh, int n, int C, int linear, int pack,
                        double2* Y1, hipStream_t s) {
   const size_t lds = sizeof(double2) * (size_t)lds_points(1 << LOGNH);
   hipError_t e = set_lds((const void*)k_cols_pass<LOGNH, R>, lds);
   if (e != hipSuccess) return e;
   const int grid = (C + 7) / 8 * 8;
   hipLaunchKernelGGL((k_cols_pass<LOGNH, R>), dim3(grid), dim3(fft_threads(1 << LOGNH, R)), lds,
-                     s, X1, Hh, n, C, linear, Y1);
+                     s, X1, Hh, n, C, linear, pack, Y1);
   return hipGetLastError();
 }
 
 // variant: bit 0 = radix-8 transforms (where they exist), bit 1 = linear
 // column order
 template <int LOGNH>
-hipError_t cols_pass_t(const double2* X1, const double2* Hh, int n, int C, int variant,
+hipError_t cols_pass_t(const double2* X1, const double2* Hh, int n, int C, int variant, int pack,
                        double2* Y1, hipStream_t s) {
   const int linear = (variant >> 1) & 1;
   if constexpr (has_radix8(LOGNH)) {
-    if (variant & 1) return cols_pass_r<LOGNH, 8>(X1, Hh, n, C, linear, Y1, s);
+    if (variant & 1) return cols_pass_r<LOGNH, 8>(X1, Hh, n, C, linear, pack, Y1, s);
   }
-  return cols_pass_r<LOGNH, 16>(X1, Hh, n, C, linear, Y1, s);
+  return cols_pass_r<LOGNH, 16>(X1, Hh, n, C, linear, pack, Y1, s);
 }
 
 #define HMV_NT_DISPATCH(FN, ...)                  \
@@ -542,18 +844,18 @@ hipError_t cols_pass_t(const double2* X1, const double2* Hh, int n, int C, int v
   }
 
 hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, double scale,
-                            double2* Hh, hipStream_t s) {
-  HMV_NT_DISPATCH(cols_plan_t, H1, rows, C, scale, Hh, s)
+                            int pack, double2* Hh, hipStream_t s) {
+  HMV_NT_DISPATCH(cols_plan_t, H1, rows, C, scale, pack, Hh, s)
 }
 
 hipError_t launch_cols_pass(const double2* X1, const double2* Hh, int n, int C, int logNt,
-                            double2* Y1, int variant, hipStream_t s) {
-  HMV_NT_DISPATCH(cols_pass_t, X1, Hh, n, C, variant, Y1, s)
+                            int pack, double2* Y1, int variant, hipStream_t s) {
+  HMV_NT_DISPATCH(cols_pass_t, X1, Hh, n, C, variant, pack, Y1, s)
 }
 
 template <int LOGM, int R>
 hipError_t rows_inv_r(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
-                      uint64_t* y, DevStatus* st, hipStream_t s) {
+                      int pack, uint64_t* y, DevStatus* st, hipStream_t s) {
   constexpr int M = 1 << LOGM;
   const int T = fft_threads(M, R);
   const int NC = 2 * L - 1;
@@ -567,29 +869,61 @@ hipError_t rows_inv_r(const double2* Y1, int n, int L, int w, int P, int W, int 
   if (e != hipSuccess) return e;
   const int grid = (n + 7) / 8 * 8;             // xcd_slot needs a multiple of 8
   hipLaunchKernelGGL((k_rows_inv<LOGM, R>), dim3(grid), dim3(T), lds, s, Y1, n, L, w, P, W,
-                     out_reverse, (int)carry_off, y, st);
+                     out_reverse, (int)carry_off, pack, y, st);
   return hipGetLastError();
 }
 
 // variant: bit 0 = radix-8 transform (where it exists)
 template <int LOGM>
 hipError_t rows_inv_t(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
-                      uint64_t* y, DevStatus* st, int variant, hipStream_t s) {
+                      int pack, uint64_t* y, DevStatus* st, int variant, hipStream_t s) {
   if constexpr (has_radix8(LOGM)) {
-    if (variant & 1) return rows_inv_r<LOGM, 8>(Y1, n, L, w, P, W, out_reverse, y, st, s);
+    if (variant & 1) return rows_inv_r<LOGM, 8>(Y1, n, L, w, P, W, out_reverse, pack, y, st, s);
   }
-  return rows_inv_r<LOGM, 16>(Y1, n, L, w, P, W, out_reverse, y, st, s);
+  return rows_inv_r<LOGM, 16>(Y1, n, L, w, P, W, out_reverse, pack, y, st, s);
 }
 
 hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
-                           int out_reverse, uint64_t* y, DevStatus* st, int variant,
+                           int out_reverse, int pack, uint64_t* y, DevStatus* st, int variant,
                            hipStream_t s) {
   switch (logM) {
 #define HMV_RI(k) \
-  case k: return rows_inv_t<k>(Y1, n, L, w, P, W, out_reverse, y, st, variant, s);
+  case k: return rows_inv_t<k>(Y1, n, L, w, P, W, out_reverse, pack, y, st, variant, s);
     HMV_RI(1) HMV_RI(2) HMV_RI(3) HMV_RI(4) HMV_RI(5) HMV_RI(6) HMV_RI(7) HMV_RI(8) HMV_RI(9)
     HMV_RI(10) HMV_RI(11) HMV_RI(12)
 #undef HMV_RI
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int LOGK>
+hipError_t rows_inv3_t(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
+                       int pack, uint64_t* y, DevStatus* st, hipStream_t s) {
+  constexpr int K = 1 << LOGK;
+  const int T = rows3_threads(K);
+  const int NC = 2 * L - 1;
+  // transform points first; afterwards NC int64 coefficients then the carry
+  // scratch
+  const size_t fft_part = sizeof(double2) * (size_t)(lds_points(K / 2) + lds_points(K));
+  const size_t carry_off = ((size_t)NC * 8 + 15) / 16 * 16;
+  const size_t carry_part = carry_off + (size_t)carry_lds_bytes(T);
+  const size_t lds = fft_part > carry_part ? fft_part : carry_part;
+  hipError_t e = set_lds((const void*)k_rows_inv3<LOGK>, lds);
+  if (e != hipSuccess) return e;
+  const int grid = (n + 7) / 8 * 8;             // xcd_slot needs a multiple of 8
+  hipLaunchKernelGGL(k_rows_inv3<LOGK>, dim3(grid), dim3(T), lds, s, Y1, n, L, w, P, W,
+                     out_reverse, (int)carry_off, pack, y, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_inv3(const double2* Y1, int n, int logK, int L, int w, int P, int W,
+                            int out_reverse, int pack, uint64_t* y, DevStatus* st,
+                            hipStream_t s) {
+  switch (logK) {
+#define HMV_RI3(k) \
+  case k: return rows_inv3_t<k>(Y1, n, L, w, P, W, out_reverse, pack, y, st, s);
+    HMV_RI3(6) HMV_RI3(7) HMV_RI3(8) HMV_RI3(9) HMV_RI3(10) HMV_RI3(11)
+#undef HMV_RI3
     default: return hipErrorInvalidValue;
   }
 }

@@ -14,6 +14,7 @@
 #include <tuple>
 
 #include "common.h"
+#include "fft_layout.h"
 #include "hmv.h"
 #include "kernels.h"
 #include "tables.h"
@@ -30,7 +31,7 @@ int ilog2_ceil(int64_t v) {
   return k;
 }
 
-bool fft_sizes(int64_t n, int32_t P, int w, FftSizes* z) {
+bool fft_sizes(int64_t n, int32_t P, int w, FftSizes* z, bool planned) {
   const int L = limbs_of(P, w);
   int logNz = ilog2_ceil(2 * int64_t(L) - 1);
   if (logNz < 2) logNz = 2;
@@ -42,6 +43,14 @@ bool fft_sizes(int64_t n, int32_t P, int w, FftSizes* z) {
   z->logM = logNz - 1;
   z->logNt = logNt;
   z->Nz = int64_t(1) << logNz;
+  z->z3 = 0;
+  // 3K points (K = 2^logK) when 2L - 1 <= 3K < 2^logNz
+  const int logK = ilog2_ceil((2 * int64_t(L) - 1 + 2) / 3);
+  if (planned && logK >= 6 && logK <= kR3MaxLogK && 3 * (int64_t(1) << logK) < z->Nz) {
+    z->z3 = 1;
+    z->logM = logK;
+    z->Nz = 3 * (int64_t(1) << logK);
+  }
   z->Nt = int64_t(1) << logNt;
   z->C = (int)(z->Nz / 2 + 1);
   z->tiles = (z->C + 7) / 8;
@@ -56,27 +65,35 @@ bool fft_sizes(int64_t n, int32_t P, int w, FftSizes* z) {
   return true;
 }
 
-// largest admissible plan over the candidate widths (smallest width = most limbs)
+// largest admissible plan over the candidate widths (smallest width = most
+// limbs) and both limb transform forms
 bool fft_worst_sizes(int64_t n, int32_t P, FftSizes* z) {
   bool any = false;
-  for (int w = kFftWMax; w >= kFftWMin; --w) {
-    FftSizes c;
-    if (!fft_sizes(n, P, w, &c)) continue;
-    if (!any) *z = c;
-    if (c.plan_bytes > z->plan_bytes) z->plan_bytes = c.plan_bytes;
-    if (c.plan_scratch > z->plan_scratch) z->plan_scratch = c.plan_scratch;
-    if (c.mv_scratch > z->mv_scratch) z->mv_scratch = c.mv_scratch;
-    any = true;
-  }
+  for (int w = kFftWMax; w >= kFftWMin; --w)
+    for (int planned = 0; planned < 2; ++planned) {
+      FftSizes c;
+      if (!fft_sizes(n, P, w, &c, planned == 1)) continue;
+      if (!any) *z = c;
+      if (c.plan_bytes > z->plan_bytes) z->plan_bytes = c.plan_bytes;
+      if (c.plan_scratch > z->plan_scratch) z->plan_scratch = c.plan_scratch;
+      if (c.mv_scratch > z->mv_scratch) z->mv_scratch = c.mv_scratch;
+      any = true;
+    }
   return any;
 }
 
-double fft_bound_for(const FftSizes& z, int64_t n, double norm_h) {
+double fft_bound_for(const FftSizes& z, int64_t n, double norm_h, int pack) {
   // worst-case x: every digit at magnitude 2^(w-1)
   const double norm_x = std::ldexp(1.0, z.w - 1) * std::sqrt((double)n * (double)z.L);
   // stages: log2(N_t) + log2(N_z) butterfly stages, plus the real-input
-  // packing / unpacking step counted as two more
-  const int k = z.logNt + (z.logM + 1) + 2;
+  // packing / unpacking step counted as two more.  For N_z = 3K the radix-3
+  // step (one tabulated root and one constant multiplication along each data
+  // path, sums that grow the norm by sqrt 3 < 2) counts as two binary stages,
+  // and the inexact 1/3 of the scaling of the resident spectrum as one more.
+  // The packed column of the two real bins adds one rounded sum or
+  // difference with the partner bin on the x side, one on the h side and one
+  // sum of two products: one more stage.
+  const int k = (z.z3 ? z.logNt + z.logM + 2 + 1 + 2 : z.logNt + (z.logM + 1) + 2) + pack;
   return fft_conv_bound(norm_h, norm_x, k, fft_twiddle_beta());
 }
 
@@ -93,6 +110,7 @@ std::mutex g_tune_mu;
 std::map<std::tuple<int, int64_t, int32_t, int>, std::pair<int, int>> g_tune_cache;
 int g_autotune = 1;
 int g_force_cols = -1, g_force_rinv = -1;       // tests: fixed variants (-1 = tune)
+int g_force_z3 = -1, g_force_pack = -1;         // tests: fixed spectrum layout (-1 = auto)
 
 bool radix8_ok(int logn) { return logn == 6 || logn == 9 || logn == 12; }
 
@@ -138,18 +156,22 @@ int fft_tune(hmv_plan* p, DevStatus* st, char* scratch, bool may_run, hipStream_
   for (int v = 0; v < kColsVariants && e == hipSuccess; ++v) {
     if ((v & 1) && !radix8_ok(p->logNt - 1)) continue;
     float ms = 0.0f;
-    e = time_launches([&] { return launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, Y1, v, s); },
-                      2, a, b, s, &ms);
+    e = time_launches(
+        [&] { return launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, p->pack, Y1, v, s); }, 2, a,
+        b, s, &ms);
     if (e == hipSuccess && (v == 0 || ms < best)) {
       best = ms;
       bc = v;
     }
   }
-  for (int v = 0; v < kRowsInvVariants && e == hipSuccess; ++v) {
+  for (int v = 0; v < kRowsInvVariants && e == hipSuccess && !p->z3; ++v) {
     if ((v & 1) && !radix8_ok(p->logM)) continue;
     float ms = 0.0f;
     e = time_launches(
-        [&] { return launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, 0, yt, st, v, s); }, 2,
+        [&] {
+          return launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, 0, p->pack, yt, st, v, s);
+        },
+        2,
         a, b, s, &ms);
     if (e == hipSuccess && (v == 0 || ms < best)) {
       best = ms;
@@ -183,10 +205,11 @@ int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
   // 1. limb norms of h for every candidate width
   unsigned long long* norms = reinterpret_cast<unsigned long long*>(scratch);
   char* h1mem = scratch + align_up(kNormSlots * 8);
+  const bool allow3 = g_force_z3 != 0;
   int wlo = kFftWMax, whi = kFftWMin;
   for (int w = kFftWMin; w <= kFftWMax; ++w) {
     FftSizes c;
-    if (fft_sizes(n, P, w, &c)) {
+    if (fft_sizes(n, P, w, &c, allow3)) {
       if (w < wlo) wlo = w;
       if (w > whi) whi = w;
     }
@@ -206,20 +229,26 @@ int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
   // 2. largest width whose proven bound is below 1/2
   FftSizes z;
   bool found = false;
-  for (int w = whi; w >= wlo; --w) {
+  int pack = 0;
+  for (int w = whi; w >= wlo && !found; --w) {
     FftSizes c;
-    if (!fft_sizes(n, P, w, &c)) continue;
+    if (!fft_sizes(n, P, w, &c, allow3)) continue;
     const double nh = std::sqrt((double)hn[w - wlo]);
-    const double b = fft_bound_for(c, n, nh);
     // every true coefficient is an integer of magnitude <= n L 4^(w-1) < 2^50
     // (the rounding step converts with a 1.5 * 2^52 offset, exact below 2^51)
     const double cmax = (double)n * c.L * std::ldexp(1.0, 2 * (w - 1));
-    if (b < 0.5 && cmax < std::ldexp(1.0, 50)) {
-      z = c;
-      p->bound = b;
-      p->norm_h = nh;
-      found = true;
-      break;
+    if (cmax >= std::ldexp(1.0, 50)) continue;
+    // the packed column where its bound allows it, else the plain layout
+    for (int pk = 1; pk >= 0 && !found; --pk) {
+      if (g_force_pack >= 0 && pk != g_force_pack) continue;
+      const double b = fft_bound_for(c, n, nh, pk);
+      if (b < 0.5) {
+        z = c;
+        pack = pk;
+        p->bound = b;
+        p->norm_h = nh;
+        found = true;
+      }
     }
   }
   if (!found) return HMV_EBOUND;
@@ -227,10 +256,12 @@ int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
   p->w = z.w;
   p->L = z.L;
   p->logM = z.logM;
+  p->z3 = z.z3;
+  p->pack = pack;
   p->logNt = z.logNt;
   p->Nt = z.Nt;
   p->Nz = z.Nz;
-  p->C = z.C;
+  p->C = z.C - pack;
   p->tiles = z.tiles;
   p->beta = fft_twiddle_beta();
   p->plan_bytes_used = z.plan_bytes;
@@ -238,15 +269,18 @@ int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
   p->Hh = reinterpret_cast<double2*>(plan_mem);
   // 3. forward 2-D transform of h, kept in the plan
   double2* H1 = reinterpret_cast<double2*>(h1mem);
-  e = launch_rows_fwd(h, W, P, z.w, z.L, rows, gather, z.logM, H1, rows, st, s);
+  e = z.z3 ? launch_rows_fwd3(h, W, P, z.w, z.L, rows, gather, z.logM, H1, rows, pack, st, s)
+           : launch_rows_fwd(h, W, P, z.w, z.L, rows, gather, z.logM, H1, rows, pack, st, s);
   if (e != hipSuccess) return status_from_hip(e, "rows fwd (h)");
-  const double scale = std::ldexp(1.0, -(z.logNt + z.logM + 1));
-  e = launch_cols_plan(H1, rows, z.C, z.logNt, scale, p->Hh, s);
+  // 1 / (N_t N_z): a power of two, or for N_z = 3K one rounding of 1/3
+  const double scale = z.z3 ? std::ldexp(1.0 / 3.0, -(z.logNt + z.logM))
+                            : std::ldexp(1.0, -(z.logNt + z.logM + 1));
+  e = launch_cols_plan(H1, rows, p->C, z.logNt, scale, pack, p->Hh, s);
   if (e != hipSuccess) return status_from_hip(e, "cols plan");
   // 4. launch variants for this shape (h's spectra stand in for x's)
   if (g_force_cols >= 0 || g_force_rinv >= 0) {
     p->cols_variant = g_force_cols >= 0 ? g_force_cols : 0;
-    p->rows_inv_variant = g_force_rinv >= 0 ? g_force_rinv : 0;
+    p->rows_inv_variant = g_force_rinv >= 0 && !z.z3 ? g_force_rinv : 0;
     return HMV_OK;
   }
   if (g_autotune) return fft_tune(p, st, scratch, may_tune, s);
@@ -266,15 +300,20 @@ int fft_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus
   double2* X1 = reinterpret_cast<double2*>(scratch);
   double2* Y1 = reinterpret_cast<double2*>(scratch + p->mv_scratch / 2);
   hipError_t e = mark(ev, 0, s);
-  if (e == hipSuccess) e = launch_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, st, s);
+  if (e == hipSuccess)
+    e = p->z3 ? launch_rows_fwd3(x, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, p->pack, st, s)
+              : launch_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, p->pack, st, s);
   if (e != hipSuccess) return status_from_hip(e, "rows fwd (x)");
   e = mark(ev, 1, s);
-  if (e == hipSuccess) e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, Y1, p->cols_variant, s);
+  if (e == hipSuccess)
+    e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, p->pack, Y1, p->cols_variant, s);
   if (e != hipSuccess) return status_from_hip(e, "cols pass");
   const int rev = (p->kind == HMV_HANKEL) ? 0 : 1;
   e = mark(ev, 2, s);
   if (e == hipSuccess)
-    e = launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, rev, y, st, p->rows_inv_variant, s);
+    e = p->z3 ? launch_rows_inv3(Y1, n, p->logM, p->L, p->w, p->P, W, rev, p->pack, y, st, s)
+              : launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, rev, p->pack, y, st,
+                                p->rows_inv_variant, s);
   if (e == hipSuccess) e = mark(ev, 3, s);
   return status_from_hip(e, "rows inv");
 }
@@ -772,6 +811,7 @@ int hmv_plan_info(const hmv_plan* p, hmv_plan_info_t* info) {
   info->matvec_workspace_bytes = kStatusBytes + p->mv_scratch;
   info->cols_variant = p->cols_variant;
   info->rows_inv_variant = p->rows_inv_variant;
+  info->spectrum_cols = p->C;
   return HMV_OK;
 }
 
@@ -781,6 +821,13 @@ int hmv_debug_force_variants(int32_t cols_variant, int32_t rows_inv_variant) {
     return HMV_EINVAL;
   g_force_cols = cols_variant;
   g_force_rinv = rows_inv_variant;
+  return HMV_OK;
+}
+
+int hmv_debug_force_layout(int32_t z3, int32_t pack) {
+  if (z3 < -1 || z3 > 1 || pack < -1 || pack > 1) return HMV_EINVAL;
+  g_force_z3 = z3;
+  g_force_pack = pack;
   return HMV_OK;
 }
 

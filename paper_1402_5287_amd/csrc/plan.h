@@ -40,8 +40,11 @@ constexpr int kNormSlots = 32;
 
 extern int g_force_w;              // tests: restrict the width candidates to one value
 
+// Limb transforms: N_z = 2^(logM+1) real points, or with z3 = 1 N_z = 3 * 2^logM
+// (a radix-3 step over two power-of-two transforms), where that is smaller
+// and still holds the 2L - 1 coefficients.
 struct FftSizes {
-  int w, L, logM, logNt, C, tiles;
+  int w, L, logM, logNt, C, tiles, z3;
   int64_t Nt, Nz;
   int64_t plan_bytes, plan_scratch, mv_scratch;
 };
@@ -58,7 +61,11 @@ struct NttSizes {
 };
 
 int ilog2_ceil(int64_t v);
-bool fft_sizes(int64_t n, int32_t P, int w, FftSizes* z);
+// planned: sizes for the planned kernels, which also take the 3 * 2^k limb
+// transform sizes (the batch kernels take powers of two).  C = N_z/2 + 1
+// columns are allocated; a plan that packs the two real limb bins into one
+// column processes C - 1 of them.
+bool fft_sizes(int64_t n, int32_t P, int w, FftSizes* z, bool planned = false);
 bool fft_worst_sizes(int64_t n, int32_t P, FftSizes* z);
 
 // planned paths (split-FFT, NTT, Karatsuba) used by the one-shot entry points
@@ -83,7 +90,8 @@ struct hmv_plan {
   int64_t n = 0;
   int32_t P = 0;
   int device = 0;
-  int w = 0, L = 0, logM = 0, logNt = 0, C = 0, tiles = 0;
+  int w = 0, L = 0, logM = 0, logNt = 0, C = 0, tiles = 0, z3 = 0;
+  int pack = 0;                    // 1: the two real limb bins share column 0 (C = N_z/2)
   int64_t Nt = 0, Nz = 0;
   double bound = 0.0, beta = 0.0, norm_h = 0.0;
   int64_t plan_bytes_used = 0, mv_scratch = 0;

@@ -89,7 +89,7 @@ void unit_root(int64_t m, int64_t N, double* re, double* im) {
   unit_root_base(m, N, re, im, &base);
 }
 
-double gen_fft_tables(double* tw, double* rtw) {
+double gen_fft_tables(double* tw, double* rtw, double* r3) {
   // worst rounding error of the roots: per first-octant entry (the other
   // entries are exact sign changes and swaps of it), over the entries used
   long double worst = 0.0L;
@@ -111,6 +111,12 @@ double gen_fft_tables(double* tw, double* rtw) {
     root(k, kRealTwN, &re, &im);
     rtw[2 * k] = re;
     rtw[2 * k + 1] = im;
+  }
+  for (int k = 0; k < kR3Entries; ++k) {
+    double re, im;
+    root(k, 3 * (int64_t)kR3MaxK, &re, &im);
+    r3[2 * k] = re;
+    r3[2 * k + 1] = im;
   }
   for (int a = 1; a <= 4; ++a)
     for (int b = 0; b < kTwSpans; ++b) {
@@ -141,6 +147,10 @@ double gen_fft_tables(double* tw, double* rtw) {
       const long double e = fabsl((long double)c[i] - ex[i]) * sqrtl(2.0L);
       if (e > worst) worst = e;
     }
+    // sqrt(3)/2 of the radix-3 step (the inverse multiplies by its double,
+    // sqrt(3), whose relative error is the same)
+    const long double e3 = fabsl((long double)0.86602540378443864676 - sqrtl(3.0L) / 2);
+    if (e3 > worst) worst = e3;
   }
   // the long double reference itself is within a few 2^-64 of the true root
   return (double)(worst + ldexpl(1.0L, -60));

@@ -9,12 +9,13 @@ namespace hmv {
 // octant reduction and rounded to binary64.
 void unit_root(int64_t m, int64_t N, double* re, double* im);
 
-// Fill the Stockham table (2 * kTwEntries doubles) and the real-packing
-// table (2 * kRealTwEntries doubles: exp(-2 pi i k / 16384), k <= 8192).
+// Fill the Stockham table (2 * kTwEntries doubles), the real-packing
+// table (2 * kRealTwEntries doubles: exp(-2 pi i k / 16384), k <= 8192) and
+// the radix-3 table (2 * kR3Entries doubles: exp(-2 pi i s / (3 kR3MaxK))).
 // Returns the largest |table - root| observed against the long double values
-// (the radix-8/16 constants included), plus a margin for the long double
-// evaluation itself: the beta of the error bound.
-double gen_fft_tables(double* tw, double* rtw);
+// (the radix-8/16 constants and sqrt(3)/2 included), plus a margin for the
+// long double evaluation itself: the beta of the error bound.
+double gen_fft_tables(double* tw, double* rtw, double* r3);
 
 // Percival-type bound on the max-norm error of a binary64 FFT convolution
 // z = IFFT(FFT(a) . FFT(b)) with transforms of 2^k points:

@@ -41,6 +41,7 @@ SIGNATURES = {
                             _vp, _c_i64, _vp]),
     "hmv_plan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp]),
     "hmv_debug_force_variants": (_c_int, [_c_i32, _c_i32]),
+    "hmv_debug_force_layout": (_c_int, [_c_i32, _c_i32]),
     "hmv_batch_launches": (_c_i32, [_vp, _c_i32]),
     "hmv_autotune": (_c_int, [_c_i32]),
     "hmv_plan_workspace_bytes": (_c_i64, [_vp]),
@@ -83,7 +84,8 @@ class PlanInfo(ctypes.Structure):
                 ("Nt", ctypes.c_int64), ("Nz", ctypes.c_int64), ("bound", ctypes.c_double),
                 ("beta", ctypes.c_double), ("norm_h", ctypes.c_double),
                 ("plan_bytes", ctypes.c_int64), ("matvec_workspace_bytes", ctypes.c_int64),
-                ("cols_variant", ctypes.c_int32), ("rows_inv_variant", ctypes.c_int32)]
+                ("cols_variant", ctypes.c_int32), ("rows_inv_variant", ctypes.c_int32),
+                ("spectrum_cols", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -260,6 +262,13 @@ def autotune(on: bool) -> None:
 def force_variants(cols: int = -1, rows_inv: int = -1) -> None:
     """Tests only: fixed split-FFT launch variants (-1, -1 = tune)."""
     _check(lib().hmv_debug_force_variants(cols, rows_inv), "force_variants")
+
+
+def force_layout(z3: int = -1, pack: int = -1) -> None:
+    """Tests only: split-FFT spectrum layout of later plans (z3 = 0: power-of-
+    two limb transforms only; pack = 0 / 1: the two real limb bins in their
+    own columns / sharing one; -1 = automatic)."""
+    _check(lib().hmv_debug_force_layout(z3, pack), "force_layout")
 
 
 def force_width(w: int) -> None:

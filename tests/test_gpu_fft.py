@@ -259,3 +259,51 @@ def test_every_launch_variant_is_exact(n, P):
     plan.matvec(xd, y)
     assert np.array_equal(hmv.to_host(y), want)
     plan.close()
+
+
+@pytest.mark.parametrize("n,P,expect3", [(33, 1000, False), (200, 1500, False),
+                                         (257, 3322, False), (1000, 33220, True)])
+def test_every_spectrum_layout_is_exact(n, P, expect3):
+    """Each spectrum layout the planner may pick gives the exact words, for
+    the three kinds: limb transforms of a power of two or of 3 * 2^k points,
+    with the two real limb bins in their own columns or sharing one.  At
+    n = 1000, P = 33220 every admissible width has 2L - 1 <= 6144 < 8192, so
+    the 3K form is taken there."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    kinds = ("hankel", "toeplitz", "circulant") if n <= 300 else ("hankel",)
+    forms = set()
+    try:
+        for kind in kinds:
+            hl = n if kind == "circulant" else 2 * n - 1
+            h = si.uniform(hl, P, (74, n, P))
+            x = si.uniform(n, P, (75, n, P))
+            if n <= 300:
+                want = hankel.matvec_words(kind, h, x, P)
+            elif kronecker.available():
+                want = kronecker.hankel_matvec_words(h, x, P)
+            else:
+                pytest.skip("GMP not available for the full-vector check")
+            hd, xd = hmv.to_device(h), hmv.to_device(x)
+            for z3 in (0, 1):
+                for pack in (0, 1):
+                    hmv.force_layout(z3, pack)
+                    plan = hmv.Plan(kind, hd, n, P, algo="split_fft")
+                    info = plan.info()
+                    Nz = info["Nz"]
+                    announce("fft layout", kind, n, P, z3, pack, info["w"], Nz,
+                             info["spectrum_cols"])
+                    assert info["spectrum_cols"] == Nz // 2 + 1 - pack
+                    if z3 == 0:
+                        assert Nz & (Nz - 1) == 0
+                    forms.add((Nz % 3 == 0, pack))
+                    y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+                    plan.matvec(xd, y)
+                    rc, flags, err = hmv.read_status(plan.ws)
+                    assert rc == 0 and flags == 0 and err < info["bound"]
+                    assert np.array_equal(hmv.to_host(y), want), (kind, z3, pack)
+                    plan.close()
+    finally:
+        hmv.force_layout(-1, -1)
+    if expect3:
+        assert (True, 0) in forms and (True, 1) in forms

@@ -46,12 +46,14 @@ def test_words_and_validation():
 
 def test_size_queries():
     hmv, L = _lib()
-    # headline shape: P = 33220 with widths 9..16 all give N_z = 8192, N_t = 8192
+    # headline shape: the sizes cover every candidate width; at P = 33220
+    # widths 9 and 10 need N_z = 8192 (N_t = 8192): 4097 resident columns,
+    # and 4096 spectrum columns per row of x and of y
     n = 4096
     pb = L.hmv_plan_bytes(0, n, 33220, 1)
     assert pb >= 8192 * 4097 * 16
     ws = L.hmv_workspace_bytes(0, n, 33220, 1)
-    assert ws >= 2 * 4096 * 4104 * 16
+    assert ws >= 2 * 4096 * 4096 * 16
     assert L.hmv_oneshot_workspace_bytes(0, 64, 3322, 4) > 0
 
 
