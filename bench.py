@@ -54,8 +54,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
+# (the split-FFT row passes of limb transforms of 3 * 2^k points are
+# k_rows_fwd3 / k_rows_inv3, see kernel_names)
 KERNEL_NAMES = {"split_fft": ("k_rows_fwd", "k_cols_pass", "k_rows_inv"),
                 "ntt": ("k_ntt_rows_fwd", "k_ntt_cols_pass", "k_ntt_rows_inv")}
+
+
+def kernel_names(algo, info):
+    if algo == "split_fft" and info["Nz"] % 3 == 0:
+        return ("k_rows_fwd3", "k_cols_pass", "k_rows_inv3")
+    return KERNEL_NAMES[algo]
 
 
 def kernel_bytes(algo, n, W, info):
@@ -196,7 +204,7 @@ def main():
     value = K / wall
 
     kb = kernel_bytes(args.algo, n, W, info)
-    names = KERNEL_NAMES[args.algo]
+    names = kernel_names(args.algo, info)
     kernels = {names[0]: (statistics.mean(k1), kb[0]), names[1]: (statistics.mean(k2), kb[1]),
                names[2]: (statistics.mean(k3), kb[2])}
     bytes_k1, bytes_k2, bytes_k3 = kb

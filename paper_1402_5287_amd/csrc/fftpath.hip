@@ -15,11 +15,12 @@
 //               reversed so the correlation becomes a convolution and rows
 //               n-1 .. 2n-2 of the cyclic result are exactly S_0 .. S_{n-1}
 //
-// Spectra between passes live in HBM in column tiles of 8 complex values:
-// element (row, k) of a [rows][C] half-plane sits at ((k/8) rows + row) 8 + k%8,
-// so a row pass writes and reads whole 128-byte lines and a column pass
-// reads one 16-byte slot per line while the 7 neighbouring columns of the
-// tile run on the same XCD (column order is remapped per XCD) and hit in its L2.
+// Spectra between passes live in HBM in column tiles of TW complex values:
+// element (row, k) of a [rows][C] half-plane sits at ((k/TW) rows + row) TW +
+// k%TW (TW = 4 for the spectra of x and of y: a row pass writes or reads 64
+// contiguous bytes of a row per tile, a column pass reads one 16-byte slot of
+// them while the TW - 1 neighbouring columns of the tile run on the same XCD,
+// column order being remapped per XCD, and hit in its L2).
 #include <mutex>
 #include <vector>
 
@@ -90,7 +91,7 @@ __device__ __forceinline__ int xcd_slot(int b, int grid) {
 // ((k / TW) rows + row) TW + k % TW.  The row passes touch TW contiguous
 // bins per row, the index-axis pass reads a bin column at stride TW.
 #ifndef HMV_X1_TILE
-#define HMV_X1_TILE 2
+#define HMV_X1_TILE 4
 #endif
 #ifndef HMV_Y1_TILE
 #define HMV_Y1_TILE 4
