@@ -521,10 +521,10 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
 //   bin 3m   = sum_s w^(3ms) u0[s],  u0[s] = x[s] + x[s+K] + x[s+2K]      (real)
 //   bin 3m+1 = sum_s w^(3ms) u1[s],  u1[s] = w^s (x[s] + r x[s+K] + r^2 x[s+2K])
 // and bin 3m+2 = conj(bin 3(K-1-m)+1) for real x.  A row stores the K/2 + 1
-// bins 3m (m <= K/2, the Hermitian half of the real K-point transform; the
-// real bins 0 and 3(K/2) share column 0) in columns 0 .. K/2-1 and the K bins
-// 3m+1 in columns K/2 .. 3K/2-1: N_z/2 columns, as for a power-of-two N_z.
-// Each limb frequency is one column of the 2-D transform.
+// bins 3m (m <= K/2, the Hermitian half of the real K-point transform) and
+// then the K bins 3m+1: N_z/2 + 1 columns, or N_z/2 when the real bins 0 and
+// 3(K/2) share column 0 (pack), as for a power-of-two N_z.  Each limb
+// frequency is one column of the 2-D transform.
 // The inverse, with z0, z1 the unnormalised inverse K-point transforms of the
 // bins 3m and 3m+1 and v[s] = w^-s z1[s]:
 //   N_z x[s + jK] = z0[s] + 2 Re(r^-j v[s]),   j = 0, 1, 2
