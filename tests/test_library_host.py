@@ -106,3 +106,13 @@ def test_twiddle_beta_against_mpmath():
                 err = abs(mpmath.mpc(float(c), float(s)) - mpmath.mpc(c, s))
                 worst = max(worst, err)
     assert float(worst) <= beta
+
+
+def test_debug_switches_validate_and_restore():
+    hmv, L = _lib()
+    assert L.hmv_debug_force_layout(2, 0) == hmv.EINVAL
+    assert L.hmv_debug_force_layout(0, -2) == hmv.EINVAL
+    assert L.hmv_debug_force_layout(0, 1) == 0
+    assert L.hmv_debug_force_layout(-1, -1) == 0
+    assert L.hmv_debug_force_variants(4, 0) == hmv.EINVAL
+    assert L.hmv_debug_force_variants(-1, -1) == 0
