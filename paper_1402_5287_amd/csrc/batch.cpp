@@ -32,14 +32,17 @@ struct InstPlan {
 
 // Limb width of a batch instance from the worst-case bound (no data read):
 // every digit of h and x at magnitude 2^(w-1).
+// The row passes take limb transforms of 3 * 2^k points where those are
+// smaller (the persistent driver, switched off, has power-of-two rows only).
 bool batch_inst_sizes(int64_t n, int32_t P, FftSizes* out) {
   if (n < 1 || n > kBatchMaxN) return false;
   for (int w = kFftWMax; w >= kFftWMin; --w) {
     FftSizes z;
-    if (!fft_sizes(n, P, w, &z)) continue;
+    if (!fft_sizes(n, P, w, &z, !kBatchPersistent)) continue;
     const double nh = std::ldexp(1.0, w - 1) * std::sqrt((double)(2 * n - 1) * (double)z.L);
     const double nx = std::ldexp(1.0, w - 1) * std::sqrt((double)n * (double)z.L);
-    const int k = z.logNt + (z.logM + 1) + 2;
+    // stages as for a plan without the shared column (fft_bound_for)
+    const int k = z.z3 ? z.logNt + z.logM + 2 + 1 + 2 : z.logNt + (z.logM + 1) + 2;
     const double b = fft_conv_bound(nh, nx, k, fft_twiddle_beta());
     const double cmax = (double)n * z.L * std::ldexp(1.0, 2 * (w - 1));
     const int NC = 2 * z.L - 1;
@@ -141,7 +144,8 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
     b.C = z.C;
     b.gather = pr.kind == HMV_CIRCULANT ? (int)pr.n : 0;
     b.reverse = pr.kind == HMV_HANKEL ? 0 : 1;
-    b.scale = std::ldexp(1.0, -(z.logNt + z.logM + 1));
+    b.scale = z.z3 ? std::ldexp(1.0 / 3.0, -(z.logNt + z.logM))
+                   : std::ldexp(1.0, -(z.logNt + z.logM + 1));
   }
   // work items, phase-major; within a pass grouped by transform size (one
   // launch per size), largest first
@@ -152,7 +156,10 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
   struct Run { int phase, logn, start, count; };
   std::vector<Run> runs;
   for (int ph = 0; ph < 4; ++ph) {
-    auto logn_of = [&](int i) { return (ph == 0 || ph == 3) ? L.ip[i].z.logM : L.ip[i].z.logNt - 1; };
+    auto logn_of = [&](int i) {
+      const FftSizes& z = L.ip[i].z;
+      return (ph == 0 || ph == 3) ? z.logM + (z.z3 ? kBatchLog3 : 0) : z.logNt - 1;
+    };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
       if (logn_of(a) != logn_of(b)) return logn_of(a) > logn_of(b);
       return (int64_t)probs[a].n * L.ip[a].z.C > (int64_t)probs[b].n * L.ip[b].z.C;
@@ -199,7 +206,7 @@ int32_t hmv_batch_launches(const hmv_problem* probs, int32_t count) {
   if (!batch_layout(probs, count, &L)) return HMV_EINVAL;
   std::vector<int> limb, index;
   for (int i = 0; i < count; ++i) {
-    limb.push_back(L.ip[i].z.logM);
+    limb.push_back(L.ip[i].z.logM + (L.ip[i].z.z3 ? kBatchLog3 : 0));
     index.push_back(L.ip[i].z.logNt - 1);
   }
   std::sort(limb.begin(), limb.end());

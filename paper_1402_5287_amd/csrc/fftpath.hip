@@ -533,15 +533,13 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
 // step; the K/2- and K-point transforms run together (fft_pair_lds).
 __host__ __device__ constexpr int rows3_threads(int K) { return K / 8 < 64 ? 64 : K / 8; }
 
-template <int LOGK>
-__global__ void __launch_bounds__(256) k_rows_fwd3(const uint64_t* __restrict__ in, int W, int P,
-                                                   int w, int L, int count, int gather_n,
-                                                   double2* __restrict__ out, int rows_alloc,
-                                                   int pack, DevStatus* st) {
-  extern __shared__ double2 buf[];
-  __shared__ uint32_t red[32];
-  const int r = xcd_slot(blockIdx.x, gridDim.x);
-  if (r >= count) return;
+// One row of the forward pass (row r of `in`, spectrum row r of `out` in
+// tiles of TW columns); blockDim.x = rows3_threads(K).
+template <int LOGK, int TW>
+__device__ __forceinline__ void row_fwd3(const uint64_t* __restrict__ in, int W, int P, int w,
+                                         int L, int gather_n, double2* __restrict__ out,
+                                         int rows_alloc, int r, int pack, double2* buf,
+                                         uint32_t* red, DevStatus* st) {
   constexpr int K = 1 << LOGK, KA = K / 2, T = rows3_threads(K), S = K / T;
   const int t = threadIdx.x;
   // the L digits (digit e in double 2 lds_slot(e/2) + e%2, the padded
@@ -583,23 +581,33 @@ __global__ void __launch_bounds__(256) k_rows_fwd3(const uint64_t* __restrict__ 
   }
   __syncthreads();
   fft_pair_lds<LOGK - 1, LOGK, T>(bufA, bufB, -1);
-  if (pack) pack_real_row<kX1Tile, true>(bufA, KA, out, r, rows_alloc);
-  else pack_real_row<kX1Tile, false>(bufA, KA, out, r, rows_alloc);
+  if (pack) pack_real_row<TW, true>(bufA, KA, out, r, rows_alloc);
+  else pack_real_row<TW, false>(bufA, KA, out, r, rows_alloc);
   const int b0 = pack ? KA : KA + 1;           // first column of the bins 3m+1
-  for (int m = t; m < K; m += T) out[tidx<kX1Tile>(b0 + m, r, rows_alloc)] = bufB[lds_slot(m)];
+  for (int m = t; m < K; m += T) out[tidx<TW>(b0 + m, r, rows_alloc)] = bufB[lds_slot(m)];
 }
 
 template <int LOGK>
-__global__ void __launch_bounds__(256) k_rows_inv3(const double2* __restrict__ Y1, int n, int L,
-                                                   int w, int P, int W, int out_reverse,
-                                                   int carry_off, int pack,
-                                                   uint64_t* __restrict__ y, DevStatus* st) {
+__global__ void __launch_bounds__(256) k_rows_fwd3(const uint64_t* __restrict__ in, int W, int P,
+                                                   int w, int L, int count, int gather_n,
+                                                   double2* __restrict__ out, int rows_alloc,
+                                                   int pack, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint32_t red[32];
+  const int r = xcd_slot(blockIdx.x, gridDim.x);
+  if (r >= count) return;
+  row_fwd3<LOGK, kX1Tile>(in, W, P, w, L, gather_n, out, rows_alloc, r, pack, buf, red, st);
+}
+
+// One row of the inverse pass (spectrum row i of Y1 in tiles of TW columns,
+// output row i, or n-1-i with out_reverse); blockDim.x = rows3_threads(K).
+template <int LOGK, int TW>
+__device__ __forceinline__ void row_inv3(const double2* __restrict__ Y1, int n, int L, int w,
+                                         int P, int W, int out_reverse, int carry_off, int pack,
+                                         uint64_t* __restrict__ y, int i, double2* buf,
+                                         uint32_t* red, DevStatus* st) {
   __shared__ RowStatus rst;
   __shared__ double2 ytop;                 // bin 3(K/2) (packed: the imaginary part of column 0)
-  const int i = xcd_slot(blockIdx.x, gridDim.x);
-  if (i >= n) return;
   row_status_init(&rst);
   constexpr int K = 1 << LOGK, KA = K / 2, T = rows3_threads(K), S = K / T;
   constexpr int SA = KA >= T ? KA / T : 1;
@@ -616,16 +624,16 @@ __global__ void __launch_bounds__(256) k_rows_inv3(const double2* __restrict__ Y
 #pragma unroll
     for (int j = 0; j < SA; ++j) {
       const int k = t + T * j;
-      va[j] = Y1[tidx<kY1Tile>(k < KA ? k : 0, i, n)];
+      va[j] = Y1[tidx<TW>(k < KA ? k : 0, i, n)];
     }
 #pragma unroll
-    for (int j = 0; j < S; ++j) vb[j] = Y1[tidx<kY1Tile>(b0 + t + T * j, i, n)];
+    for (int j = 0; j < S; ++j) vb[j] = Y1[tidx<TW>(b0 + t + T * j, i, n)];
     if (t == 0) {
       if (pack) {
         ytop = make_double2(va[0].y, 0.0);
         va[0] = make_double2(va[0].x, 0.0);
       } else {
-        ytop = Y1[tidx<kY1Tile>(KA, i, n)];
+        ytop = Y1[tidx<TW>(KA, i, n)];
       }
     }
 #pragma unroll
@@ -697,6 +705,18 @@ __global__ void __launch_bounds__(256) k_rows_inv3(const double2* __restrict__ Y
   int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
   const int row = out_reverse ? (n - 1 - i) : i;
   carry_round_pack_fit(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
+}
+
+template <int LOGK>
+__global__ void __launch_bounds__(256) k_rows_inv3(const double2* __restrict__ Y1, int n, int L,
+                                                   int w, int P, int W, int out_reverse,
+                                                   int carry_off, int pack,
+                                                   uint64_t* __restrict__ y, DevStatus* st) {
+  extern __shared__ double2 buf[];
+  __shared__ uint32_t red[32];
+  const int i = xcd_slot(blockIdx.x, gridDim.x);
+  if (i >= n) return;
+  row_inv3<LOGK, kY1Tile>(Y1, n, L, w, P, W, out_reverse, carry_off, pack, y, i, buf, red, st);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1286,6 +1306,61 @@ __global__ void __launch_bounds__(256, 2) k_batch_rows_inv(const BatchInst* __re
   b_row_inv(I.Y1, I.n, I.logM, I.L, I.w, I.P, I.W, I.reverse, I.y, d.z, buf, red, st);
 }
 
+// The row passes of instances whose limb transform has 3K = 3 * 2^LOGK
+// points (the planned path's row bodies, with the batch's tiles of 8 columns
+// and no shared column for the real bins).
+template <int LOGK>
+__global__ void __launch_bounds__(256) k_batch_rows_fwd3(const BatchInst* __restrict__ inst,
+                                                         const int4* __restrict__ items,
+                                                         int nitems, DevStatus* st) {
+  extern __shared__ double2 buf[];
+  __shared__ uint32_t red[32];
+  const int it = blockIdx.x;
+  if (it >= nitems) return;
+  const int4 d = items[it];
+  const BatchInst I = inst[d.x];
+  const int rows_h = 2 * I.n - 1;
+  if (d.z < rows_h)
+    row_fwd3<LOGK, 8>(I.h, I.W, I.P, I.w, I.L, I.gather, I.H1, rows_h, d.z, 0, buf, red, st);
+  else
+    row_fwd3<LOGK, 8>(I.x, I.W, I.P, I.w, I.L, 0, I.X1, I.n, d.z - rows_h, 0, buf, red, st);
+}
+
+template <int LOGK>
+__global__ void __launch_bounds__(256) k_batch_rows_inv3(const BatchInst* __restrict__ inst,
+                                                         const int4* __restrict__ items,
+                                                         int nitems, DevStatus* st) {
+  extern __shared__ double2 buf[];
+  __shared__ uint32_t red[32];
+  const int it = blockIdx.x;
+  if (it >= nitems) return;
+  const int4 d = items[it];
+  const BatchInst I = inst[d.x];
+  // the coefficients (2L - 1 <= 3K int64) fit in the transform buffer; the
+  // carry scratch follows it
+  constexpr int K = 1 << LOGK;
+  const int carry_off = (int)sizeof(double2) * (lds_points(K / 2) + lds_points(K));
+  row_inv3<LOGK, 8>(I.Y1, I.n, I.L, I.w, I.P, I.W, I.reverse, carry_off, 0, I.y, d.z, buf, red,
+                    st);
+}
+
+template <int LOGK>
+hipError_t batch_rows3_t(int phase, const BatchInst* inst, const int4* items, int nitems,
+                         DevStatus* st, hipStream_t s) {
+  constexpr int K = 1 << LOGK;
+  const int T = rows3_threads(K);
+  size_t lds = sizeof(double2) * (size_t)(lds_points(K / 2) + lds_points(K));
+  if (phase == 3) lds += (size_t)carry_lds_bytes(T) + 16;
+  const void* fn = phase == 0 ? (const void*)k_batch_rows_fwd3<LOGK> : (const void*)k_batch_rows_inv3<LOGK>;
+  hipError_t e = set_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  if (phase == 0)
+    hipLaunchKernelGGL(k_batch_rows_fwd3<LOGK>, dim3(nitems), dim3(T), lds, s, inst, items, nitems, st);
+  else
+    hipLaunchKernelGGL(k_batch_rows_inv3<LOGK>, dim3(nitems), dim3(T), lds, s, inst, items, nitems, st);
+  return hipGetLastError();
+}
+
 // Items of one pass whose transforms have 2^logn points (the limb transform
 // for passes 0 and 3, the index-axis half for passes 1 and 2).
 hipError_t launch_batch_phase(int phase, int logn, const BatchInst* inst, const int4* items,
@@ -1293,6 +1368,15 @@ hipError_t launch_batch_phase(int phase, int logn, const BatchInst* inst, const 
   if (nitems <= 0) return hipSuccess;
   hipError_t e = fft_tables_init();
   if (e != hipSuccess) return e;
+  if ((phase == 0 || phase == 3) && logn >= kBatchLog3) {
+    switch (logn - kBatchLog3) {
+#define HMV_BR3(k) \
+  case k: return batch_rows3_t<k>(phase, inst, items, nitems, st, s);
+      HMV_BR3(6) HMV_BR3(7) HMV_BR3(8) HMV_BR3(9) HMV_BR3(10) HMV_BR3(11)
+#undef HMV_BR3
+      default: return hipErrorInvalidValue;
+    }
+  }
   const int N = 1 << logn;
   const int T = fft_threads(N, 16);
   const void* fn = phase == 0   ? (const void*)k_batch_rows_fwd

@@ -107,7 +107,9 @@ constexpr size_t kBatchDynLds = 72 * 1024;   // dynamic LDS of the batch kernel
 hipError_t launch_batch(const BatchInst* inst, const int4* items, int nitems, int* head, int* ctr,
                         int nctr, int grid, int spin_limit, DevStatus* st, hipStream_t s);
 // one pass (0 forward rows, 1 plan columns, 2 matvec columns, 3 inverse rows)
-// over items whose transforms have 2^logn points
+// over items whose transforms have 2^logn points; for the row passes,
+// logn = kBatchLog3 + k stands for limb transforms of 3 * 2^k points
+constexpr int kBatchLog3 = 16;
 hipError_t launch_batch_phase(int phase, int logn, const BatchInst* inst, const int4* items,
                               int nitems, DevStatus* st, hipStream_t s);
 
