@@ -92,8 +92,10 @@ int hmv_circulant_matvec(const uint64_t* c, const uint64_t* x, uint64_t* y, int6
  * Lanczos iteration, Section 1) pays for it once.
  *
  * hmv_plan_bytes / hmv_workspace_bytes give sizes that hold for every limb
- * width the planner may pick (the width depends on the data of h through
- * the error bound).  plan_mem must stay valid and unmodified while the plan
+ * width and spectrum layout the planner may pick (the width depends on the
+ * data of h through the error bound; the layout, limb transforms of a power
+ * of two or of 3 * 2^k points, on the width); hmv_plan_info reports the
+ * bytes the plan actually uses.  plan_mem must stay valid and unmodified while the plan
  * is used; ws is scratch for plan_h and for each plan_matvec, and its first
  * 256 bytes receive the device status of that call.  hmv_plan_h synchronises
  * `stream` once (limb norms); hmv_plan_matvec is fully asynchronous.  A plan
