@@ -205,8 +205,13 @@ typedef struct {
 
 int hmv_server_create(hmv_server** out, void* pool, int64_t pool_bytes, int32_t max_slots);
 int hmv_server_add_plan(hmv_server* server, const hmv_plan* plan, int32_t* matrix_id);
+/* hmv_server_submit orders the request after all work enqueued on
+ * `stream` (a hipStream_t, NULL = the null stream) before the call, as the
+ * other entry points do: the server records an event there and the
+ * request's kernels wait on it, so x may be written (and y last read) by
+ * work still queued on that stream.                                        */
 int hmv_server_submit(hmv_server* server, int32_t matrix_id, int64_t session, const uint64_t* x,
-                      uint64_t* y, int64_t* request_id);
+                      uint64_t* y, void* stream, int64_t* request_id);
 int hmv_server_poll(hmv_server* server, int64_t* done_ids, int32_t* done_status, int32_t cap,
                     int32_t* n_done);
 int hmv_server_stats(const hmv_server* server, hmv_server_stats_t* stats);
@@ -239,10 +244,18 @@ int hmv_debug_force_layout(int32_t z3, int32_t pack);
 int hmv_debug_batch_spin_limit(int32_t spins);
 
 /* Device status of the last call that used workspace `ws`: synchronises
- * `stream`, stores the ST flags (bit 0 range, bit 1 bound, bit 2 spin limit)
- * and, for the split-FFT path, the largest distance of an FFT output
- * coefficient from its nearest integer.  Either out pointer may be NULL.
- * Returns HMV_ERANGE if an input was out of range, else HMV_OK.            */
+ * `stream`, stores the ST flags (bit 0 range, bit 1 bound, bit 2 spin limit,
+ * bit 3 overflow) and, for the split-FFT path, the largest distance of an
+ * FFT output coefficient from its nearest integer.  Either out pointer may
+ * be NULL.  Returns, in this order of precedence:
+ *   HMV_ERANGE  an input had |value| > 1 (y is unspecified);
+ *   HMV_EBOUND  a transform output was not a trustworthy integer: a
+ *               coefficient reached the planner's magnitude limit, a slot
+ *               that must be zero was not, or a binary64 output lay more
+ *               than 1/4 from its nearest integer (far outside the proven
+ *               bound) -- y must not be used;
+ *   HMV_EDEVICE a bounded device wait gave up (spin limit);
+ *   HMV_OK      otherwise.                                                  */
 int hmv_read_status(const void* ws, void* stream, int32_t* flags, double* max_round_err);
 
 #ifdef __cplusplus

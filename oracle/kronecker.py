@@ -94,7 +94,9 @@ def hankel_sums(h_words, x_words, P: int) -> list:
     n = x_words.shape[0]
     if h_words.shape[0] != 2 * n - 1:
         raise ValueError("Hankel vector must have 2n-1 entries")
-    fp.check_range(fp.decode(h_words[:1]), P)
+    # every entry is range-checked: the slot width below assumes |X| <= 2**P
+    fp.check_range(fp.decode(h_words), P)
+    fp.check_range(fp.decode(x_words), P)
     # |S_i| <= n 2**(2P); slot needs 2P + log2(n) + 2 bits, rounded up to words
     Wb = max((2 * P + n.bit_length() + 2 + 63) // 64, h_words.shape[1])
     g = _lib()

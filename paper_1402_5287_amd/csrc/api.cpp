@@ -201,7 +201,10 @@ int hmv_read_status(const void* ws, void* stream, int32_t* flags, double* max_ro
     std::memcpy(&d, &host.max_err_bits, sizeof(d));
     *max_round_err = d;
   }
-  return (host.flags & ST_RANGE) ? HMV_ERANGE : HMV_OK;
+  if (host.flags & ST_RANGE) return HMV_ERANGE;
+  if (host.flags & (ST_BOUND | ST_OVERFLOW)) return HMV_EBOUND;
+  if (host.flags & ST_SPIN) return HMV_EDEVICE;
+  return HMV_OK;
 }
 
 }  // extern "C"

@@ -1,7 +1,10 @@
-// Batched launch: many independent (kind, n, P) products, every instance's
-// work items of one pass in one launch (four launches in all), with the
-// host-side sizing, descriptors and item lists.  A single persistent launch
-// with a device work queue is kept in the source but switched off.
+// Batched launches: many independent (kind, n, P) products.  One launch
+// covers the work items of one pass whose transforms have the same size, for
+// every instance of that size (hmv_batch_launches counts them: 24 for the
+// 256-instance mix of four precisions).  Also the host-side sizing,
+// descriptors and item lists.  A single persistent launch with a device work
+// queue is kept in the source but switched off: it did not finish on two
+// runs and the cause is unknown.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -28,7 +28,9 @@ __device__ inline void status_or(DevStatus* st, uint32_t f) {
   if (st) atomicOr(&st->flags, f);
 }
 
-// Per-row status of the rounding step.  Every thread folds its largest
+// Per-row status of the rounding step.  ST_BOUND is raised when a
+// coefficient is out of its range (`bad`) or lies more than 1/4 from its
+// nearest integer.  Every thread folds its largest
 // rounding distance into one of 16 LDS slots (LDS atomics on 16 addresses,
 // so at most 16 threads contend for one); the bound flag rides on the
 // barrier.  Thread 0 then publishes both with at most one global atomic
@@ -61,7 +63,9 @@ __device__ __forceinline__ void row_status_publish(RowStatus* rs, double err, in
     // a non-returning atomic: the work-group does not wait for it
     unsigned long long* dst = reinterpret_cast<unsigned long long*>(&st->max_err_bits);
     if (bits) atomicMax(dst, bits);
-    if (bad) status_or(st, ST_BOUND);
+    // a rounding distance above 1/4 is far outside the proven bound: the
+    // nearest integer may not be the exact coefficient, so y is not trusted
+    if (bad || __longlong_as_double((long long)bits) > 0.25) status_or(st, ST_BOUND);
   }
 }
 

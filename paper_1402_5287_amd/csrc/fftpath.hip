@@ -960,12 +960,13 @@ hipError_t launch_rows_inv3(const double2* Y1, int n, int logK, int L, int w, in
 //   phase 2  index-axis pass of one limb column of X1 against Hh (-> Y1)
 //   phase 3  inverse row transform + exact carry of one output row (-> y)
 // Two drivers share the item code: a phase-synchronous one (one launch per
-// phase, the one in use) and a single persistent launch in which
-// work-groups take items from a global counter and wait on per-instance
-// completion counters (bounded: past the spin limit it flags ST_SPIN and
-// moves on).  The persistent driver is switched off: on this part each
-// cross-XCD hand-off needs a full L2 write-back / invalidate, which made it
-// far slower than the phase-synchronous launches.
+// pass and transform size, the one in use) and a single persistent launch in
+// which work-groups take items from a global counter and wait on
+// per-instance completion counters (bounded: past the spin limit it flags
+// ST_SPIN and moves on).  The persistent driver is switched off and
+// unreachable: its launch did not finish on either of two runs (the second
+// after its counters and fences were moved to system scope), and the cause
+// of that has not been established.
 namespace hmv {
 
 // Counters and the hand-off of results use system-scope atomics and

@@ -85,6 +85,7 @@ struct Request {
   const uint64_t* x = nullptr;
   uint64_t* y = nullptr;
   int64_t ws_off = -1, ws_bytes = 0;
+  hipEvent_t ready = nullptr;   // recorded on the submitter's stream at submit
 };
 
 struct Slot {
@@ -102,6 +103,7 @@ struct hmv_server {
   std::vector<Slot> slots;
   std::vector<const hmv_plan*> plans;
   std::deque<Request> waiting;
+  std::vector<hipEvent_t> spare_events;   // recycled ordering events
   std::set<int64_t> busy_sessions;
   int64_t next_id = 1;
   int64_t completed = 0, admitted = 0;
@@ -143,7 +145,9 @@ int admit(hmv_server* S) {
     r.ws_off = off;
     Slot& sl = S->slots[slot];
     const hmv_plan* p = S->plans[r.mid];
-    int rc = hmv_plan_matvec(p, r.x, r.y, S->pool + off, r.ws_bytes, sl.stream);
+    // the request starts after the submitter's work that preceded submit
+    int rc = hipStreamWaitEvent(sl.stream, r.ready, 0) == hipSuccess ? HMV_OK : HMV_EDEVICE;
+    if (rc == HMV_OK) rc = hmv_plan_matvec(p, r.x, r.y, S->pool + off, r.ws_bytes, sl.stream);
     if (rc == HMV_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) rc = HMV_EDEVICE;
     if (rc != HMV_OK) {
       S->alloc.release(off, need);
@@ -193,9 +197,24 @@ int hmv_server_add_plan(hmv_server* S, const hmv_plan* plan, int32_t* matrix_id)
 }
 
 int hmv_server_submit(hmv_server* S, int32_t matrix_id, int64_t session, const uint64_t* x,
-                      uint64_t* y, int64_t* request_id) {
+                      uint64_t* y, void* stream, int64_t* request_id) {
   if (!S || !x || !y || matrix_id < 0 || matrix_id >= (int32_t)S->plans.size()) return HMV_EINVAL;
+  clear_stale_error();
+  hipEvent_t ev = nullptr;
+  if (!S->spare_events.empty()) {
+    ev = S->spare_events.back();
+    S->spare_events.pop_back();
+  } else {
+    const hipError_t ec = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (ec != hipSuccess) return status_from_hip(ec, "server event");
+  }
+  const hipError_t er = hipEventRecord(ev, static_cast<hipStream_t>(stream));
+  if (er != hipSuccess) {
+    S->spare_events.push_back(ev);
+    return status_from_hip(er, "server submit event");
+  }
   Request r;
+  r.ready = ev;
   r.id = S->next_id++;
   r.mid = matrix_id;
   r.session = session;
@@ -204,7 +223,6 @@ int hmv_server_submit(hmv_server* S, int32_t matrix_id, int64_t session, const u
   r.ws_bytes = kStatusBytes + S->plans[matrix_id]->mv_scratch;
   S->waiting.push_back(r);
   if (request_id) *request_id = r.id;
-  clear_stale_error();
   return admit(S);
 }
 
@@ -224,6 +242,7 @@ int hmv_server_poll(hmv_server* S, int64_t* done_ids, int32_t* done_status, int3
     if (done_status) done_status[*n_done] = rc == HMV_OK ? flags : rc;
     ++*n_done;
     S->alloc.release(sl.req.ws_off, align_up(sl.req.ws_bytes));
+    S->spare_events.push_back(sl.req.ready);   // its wait has been consumed
     S->busy_sessions.erase(sl.req.session);
     sl.busy = false;
     ++S->completed;
@@ -250,9 +269,13 @@ int hmv_server_destroy(hmv_server* S) {
   if (!S) return HMV_EINVAL;
   for (auto& sl : S->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.busy && sl.req.ready) (void)hipEventDestroy(sl.req.ready);
     if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
+  for (auto& r : S->waiting)
+    if (r.ready) (void)hipEventDestroy(r.ready);
+  for (hipEvent_t ev : S->spare_events) (void)hipEventDestroy(ev);
   delete S;
   return HMV_OK;
 }

@@ -56,7 +56,7 @@ SIGNATURES = {
     "hmv_batch_matvec": (_c_int, [_vp, _c_i32, _vp, _c_i64, _vp]),
     "hmv_server_create": (_c_int, [ctypes.POINTER(_vp), _vp, _c_i64, _c_i32]),
     "hmv_server_add_plan": (_c_int, [_vp, _vp, ctypes.POINTER(_c_i32)]),
-    "hmv_server_submit": (_c_int, [_vp, _c_i32, _c_i64, _vp, _vp, ctypes.POINTER(_c_i64)]),
+    "hmv_server_submit": (_c_int, [_vp, _c_i32, _c_i64, _vp, _vp, _vp, ctypes.POINTER(_c_i64)]),
     "hmv_server_poll": (_c_int, [_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i32), _c_i32,
                                  ctypes.POINTER(_c_i32)]),
     "hmv_server_stats": (_c_int, [_vp, _vp]),
@@ -332,10 +332,12 @@ class Server:
         self.plans.append(plan)
         return int(mid.value)
 
-    def submit(self, matrix_id: int, session: int, x, y) -> int:
+    def submit(self, matrix_id: int, session: int, x, y, stream=None) -> int:
+        """Queue one matvec; it runs after the work already queued on `stream`
+        (torch's current stream by default), e.g. the kernel that wrote x."""
         rid = _c_i64(0)
         _check(lib().hmv_server_submit(self.handle, matrix_id, session, _ptr(x), _ptr(y),
-                                       ctypes.byref(rid)), "submit")
+                                       _stream(stream), ctypes.byref(rid)), "submit")
         return int(rid.value)
 
     def poll(self, cap: int = 64):

@@ -307,3 +307,50 @@ def test_every_spectrum_layout_is_exact(n, P, expect3):
         hmv.force_layout(-1, -1)
     if expect3:
         assert (True, 0) in forms and (True, 1) in forms
+
+
+def test_graph_captured_planned_step():
+    """A planned matvec at the session shape (n = 4096, P = 33220) captured in
+    a HIP graph: three replays, each on a different x copied into the
+    captured input buffer (with eager work and synchronisations between the
+    replays), each equal to the eager result and to the GMP product."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    if not kronecker.available():
+        pytest.skip("GMP not available for the full-vector check")
+    n, P = 4096, 33220
+    h = si.session_h(n, P)
+    plan = hmv.Plan("hankel", hmv.to_device(h), n, P, algo="split_fft")
+    W = hmv.words(P)
+    xs = [si.session_x(n, P, k) for k in (3, 4, 5)]
+    xg = torch.zeros((n, W), dtype=torch.int64, device="cuda")
+    yg = torch.zeros_like(xg)
+    announce("graph capture", n, P)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        xg.copy_(hmv.to_device(xs[0]))
+        plan.matvec(xg, yg)                 # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.matvec(xg, yg)
+    torch.cuda.synchronize()
+    ye = torch.zeros_like(xg)
+    for k, x in enumerate(xs):
+        announce("graph replay", k)
+        xg.copy_(hmv.to_device(x))
+        yg.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = hmv.to_host(yg)
+        rc, flags, err = hmv.read_status(plan.ws)
+        assert rc == 0 and flags == 0 and err < 0.25, k
+        plan.matvec(hmv.to_device(x), ye)   # eager, same plan and workspace
+        torch.cuda.synchronize()
+        assert np.array_equal(got, hmv.to_host(ye)), k
+        assert np.array_equal(got, kronecker.hankel_matvec_words(h, x, P)), k
+    del g
+    plan.close()

@@ -1,6 +1,7 @@
 """Request scheduler (continuous batching of Lanczos-shaped sessions): every
 result of the mixed run equals the same request run alone."""
 import random
+import time
 
 import numpy as np
 import pytest
@@ -16,7 +17,7 @@ def test_mixed_sessions_equal_alone():
     need_gpu()
     from paper_1402_5287_amd import hmv, serving
     mats = [("hankel", 64, 3322), ("toeplitz", 300, 1024), ("circulant", 1000, 3322),
-            ("hankel", 700, 700)]
+            ("hankel", 700, 700), ("hankel", 4000, 33220), ("hankel", 8000, 33220)]
     plans, host_h = [], []
     for i, (kind, n, P) in enumerate(mats):
         hl = n if kind == "circulant" else 2 * n - 1
@@ -31,7 +32,7 @@ def test_mixed_sessions_equal_alone():
     sessions, host_x = [], {}
     arr = serving.poisson_arrivals(400.0, 10, rng)
     for sid in range(10):
-        m = rng.randrange(len(mats))
+        m = sid if sid < len(mats) else rng.randrange(len(mats))   # every matrix is used
         kind, n, P = mats[m]
         xs, ys = [], []
         for k in range(rng.randint(3, 8)):
@@ -71,3 +72,40 @@ def test_pool_too_small_is_refused():
         server.add_plan(plan)
     assert ei.value.code == hmv.ENOMEM
     server.close()
+
+
+def test_submit_waits_for_the_producer_stream():
+    """x is written by a torch kernel queued behind a long-running one on the
+    submitting stream, and the request is submitted right after: the server
+    must order the request after that write (the result equals the product
+    of the new x, not of the stale buffer)."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    n, P = 1000, 3322
+    h = si.uniform(2 * n - 1, P, (93, 0))
+    plan = hmv.Plan("hankel", hmv.to_device(h), n, P)
+    server = hmv.Server(pool_bytes=4 * plan.mv_ws_bytes, slots=2)
+    mid = server.add_plan(plan)
+    W = hmv.words(P)
+    for k in range(3):
+        xsrc = hmv.to_device(si.uniform(n, P, (93, 1, k)))
+        x = torch.zeros((n, W), dtype=torch.int64, device="cuda")
+        y = torch.zeros_like(x)
+        torch.cuda.synchronize()
+        announce("serving producer order", k)
+        torch.cuda._sleep(200_000_000)          # keeps the stream busy for a while
+        x.copy_(xsrc)                           # the producer write, queued behind it
+        rid = server.submit(mid, k, x, y)
+        done, t0 = [], time.time()
+        while not done:
+            assert time.time() - t0 < 60.0, "request not retired"
+            done = server.poll()
+        assert done == [(rid, 0)]
+        torch.cuda.synchronize()
+        alone = torch.zeros_like(y)
+        plan.matvec(xsrc, alone, ws=plan.new_workspace())
+        torch.cuda.synchronize()
+        assert torch.equal(alone, y), k
+        assert torch.count_nonzero(y).item() > 0
+    server.close()
+    plan.close()

@@ -290,6 +290,63 @@ def test_kronecker_equals_schoolbook():
         assert kronecker.hankel_sums(h, x, P) == want
 
 
+@pytest.mark.skipif(not kronecker.available(), reason="libgmp not present")
+def test_kronecker_equals_schoolbook_n1024():
+    """The Kronecker cross-check against the plain sums at n = 1024 (every
+    row), the size it must reach before it is trusted at n = 4096."""
+    n, P = 1024, 1024
+    h = si.uniform(2 * n - 1, P, (79, 0))
+    x = si.uniform(n, P, (79, 1))
+    assert kronecker.hankel_sums(h, x, P) == hankel.hankel_sums(fp.decode(h), fp.decode(x))
+
+
+@pytest.mark.skipif(not kronecker.available(), reason="libgmp not present")
+def test_kronecker_rows_at_headline_size():
+    """n = 4096, P = 33220: the Kronecker product equals the plain row sums
+    on sampled rows (first, an interior one, last), computed over a pool."""
+    n, P = 4096, 33220
+    h = si.uniform(2 * n - 1, P, (80, 0))
+    x = si.uniform(n, P, (80, 1))
+    rows = [0, 1777, n - 1]
+    sums = kronecker.hankel_sums(h, x, P)
+    got = [fp.round_half_even(sums[i], P) for i in rows]
+    assert got == hankel.matvec_rows("hankel", fp.decode(h), fp.decode(x), P, rows, processes=3)
+
+
+def test_kronecker_range_checks_every_entry():
+    n, P = 6, 64
+    h = si.uniform(2 * n - 1, P, (81, 0))
+    x = si.uniform(n, P, (81, 1))
+    for arr, k in ((h, 2 * n - 2), (x, n - 1), (x, 0)):
+        bad = arr.copy()
+        bad[k:k + 1] = si.ints_to_words([(1 << P) + 1], P)
+        args = (bad, x) if arr is h else (h, bad)
+        with pytest.raises(ValueError):
+            kronecker.hankel_sums(args[0], args[1], P)
+
+
+@pytest.mark.parametrize("kind", ["hankel", "toeplitz", "circulant"])
+@pytest.mark.parametrize("processes", [1, 4])
+def test_row_sampled_oracle_equals_full_oracle(kind, processes):
+    """matvec_rows (the row-sampled oracle behind every large-n check) equals
+    matvec_ints row by row, for all three matrix kinds; at n <= 8 both also
+    equal exact rationals from the matrix displays."""
+    rng = random.Random(31 + processes + len(kind))
+    for n, P in ((1, 9), (2, 64), (7, 65), (33, 200), (300, 130)):
+        alen = n if kind == "circulant" else 2 * n - 1
+        a = _rand_vals(rng, alen, P)
+        x = _rand_vals(rng, n, P)
+        full = hankel.matvec_ints(kind, a, x, P)
+        rows = list(range(n)) if n <= 33 else sorted(rng.sample(range(n), 40) + [0, n - 1])
+        assert hankel.matvec_rows(kind, a, x, P, rows, processes=processes) == \
+            [full[i] for i in rows], (kind, n)
+        if n <= 8:
+            A = _matrix(kind, [Fraction(v, 1 << P) for v in a], n)
+            xf = [Fraction(v, 1 << P) for v in x]
+            assert full == [round(sum(A[i][j] * xf[j] for j in range(n)) * (1 << P))
+                            for i in range(n)]
+
+
 # ---------------------------------------------------------------------------
 # planted mistakes: each pin above must reject a plausible wrong oracle
 # ---------------------------------------------------------------------------
@@ -323,14 +380,28 @@ def test_pins_reject_planted_mistakes(monkeypatch):
                         lambda S, P: (S + (1 << (P - 1))) >> P if S >= 0 else -((-S + (1 << (P - 1))) >> P))
     assert hankel.matvec_ints("hankel", [5], [1 << 9], 10) != [2]
     monkeypatch.undo()
-    # (4) Algorithm 1 with a sign error in the even-row combine
-    orig = alg1._alg1
+    # (4) Algorithm 1 with a sign error in the combine of its second row
+    orig = alg1._half_products
 
-    def bad(nn, aa, xx, n0):
-        y = orig(nn, aa, xx, n0)
-        if nn > n0 and nn >= 4:
-            y[2] = -y[2]
+    def bad(aa, xx, n0):
+        y = orig(aa, xx, n0)
+        if len(xx) > n0 and len(xx) >= 4:
+            y[1] = -y[1]
         return y
-    monkeypatch.setattr(alg1, "_alg1", bad)
+    monkeypatch.setattr(alg1, "_half_products", bad)
     assert alg1.alg1(9, list(range(1, 18)), list(range(1, 10))) != \
         hankel.hankel_sums(list(range(1, 18)), list(range(1, 10)))
+    monkeypatch.undo()
+    # (5) the row-sampled oracle with a wrong circulant index ((i + j) mod n)
+    orig_row = hankel._row_value
+
+    def bad_row(kind, H, X, i, P):
+        if kind == "circulant":
+            nn = len(X)
+            return fp.round_half_even(sum(H[(i + j) % nn] * X[j] for j in range(nn)), P)
+        return orig_row(kind, H, X, i, P)
+    monkeypatch.setattr(hankel, "_row_value", bad_row)
+    c = [5, -3, 11, 2]
+    xx = [1, 4, -2, 7]
+    assert hankel.matvec_rows("circulant", c, xx, 4, range(4)) != \
+        hankel.matvec_ints("circulant", c, xx, 4)
