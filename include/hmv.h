@@ -19,9 +19,11 @@
  *
  * MEMORY.  Every array argument (h, x, y, workspaces, plan memory) is a
  * DEVICE pointer owned by the caller; the library never allocates device
- * memory.  Sizes come from the *_bytes queries.  y must not alias h, x or a
- * workspace.  Work is enqueued on `stream` (a hipStream_t; NULL = the null
- * stream); outputs are valid once the stream has synchronised.
+ * memory (hmv_plan_matvec_noalloc takes its workspace from a fixed array
+ * inside the library instead).  Sizes come from the *_bytes queries.  y
+ * must not alias h, x or a workspace.  Work is enqueued on `stream` (a
+ * hipStream_t; NULL = the null stream); outputs are valid once the stream
+ * has synchronised.
  *
  * ERRORS.  Calls return an hmv_status code and never throw.  Argument errors
  * (n < 1, P outside [1, HMV_MAX_P], null pointers, short buffers, unknown
@@ -149,6 +151,27 @@ int64_t hmv_plan_workspace_bytes(const hmv_plan* plan);
 int hmv_autotune(int32_t on);
 int hmv_plan_info(const hmv_plan* plan, hmv_plan_info_t* info);
 int hmv_plan_destroy(hmv_plan* plan);
+
+/* ---------------------------------------------------------------- no allocation
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * result as hmv_plan_matvec, but the workspace is a fixed array of
+ * HMV_NOALLOC_BYTES bytes inside the library (one per device, loaded on the
+ * first call there and held until the process ends), so the caller passes
+ * only the plan, x and y, plus an optional 256-byte device buffer `status`
+ * that receives the device status of the call (read it with
+ * hmv_read_status(status, ...)); with status == NULL the status block stays
+ * in the fixed array.  The call allocates nothing and is asynchronous on
+ * `stream`.  Returns HMV_ENOMEM (message in hmv_last_error) when the plan
+ * needs more than HMV_NOALLOC_BYTES of workspace (hmv_plan_workspace_bytes:
+ * n = 4096 at P = 33220 needs 385 MiB and fits), HMV_EINVAL when the plan
+ * belongs to another device than the current one.  Every call on a device
+ * shares that one array and leaves its contents behind (each call rewrites
+ * all of what it reads): calls that overlap on one device -- on two streams,
+ * or from two threads -- race and must be serialised by the caller.      */
+#define HMV_NOALLOC_BYTES (448ll << 20)
+int hmv_plan_matvec_noalloc(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* status,
+                            void* stream);
 
 /* ---------------------------------------------------------------- batches
  * Many independent products (any mix of kinds, n and P).  The work of all

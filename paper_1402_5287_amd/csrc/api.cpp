@@ -58,6 +58,11 @@ int status_from_hip(hipError_t e, const char* where) {
 
 void clear_stale_error() { (void)hipGetLastError(); }
 
+int fail_with(int code, const char* msg) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg ? msg : "");
+  return code;
+}
+
 }  // namespace hmv
 
 namespace {

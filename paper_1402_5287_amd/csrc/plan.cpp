@@ -768,14 +768,20 @@ int plan_matvec_impl(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, void* 
                      int64_t ws_bytes, hipStream_t s, void* const* events, bool clear) {
   if (!p || !x || !y || !ws) return HMV_EINVAL;
   if (ws_bytes < kStatusBytes) return HMV_ENOMEM;
+  return plan_matvec_parts(p, x, y, static_cast<DevStatus*>(ws),
+                           static_cast<char*>(ws) + kStatusBytes, ws_bytes - kStatusBytes, s,
+                           events, clear);
+}
+
+int plan_matvec_parts(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
+                      char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* events,
+                      bool clear) {
+  if (!p || !x || !y || !st || !scratch) return HMV_EINVAL;
   clear_stale_error();
-  DevStatus* st = static_cast<DevStatus*>(ws);
   if (clear) {
     hipError_t e = launch_clear_status(st, s);
     if (e != hipSuccess) return status_from_hip(e, "clear status");
   }
-  char* scratch = static_cast<char*>(ws) + kStatusBytes;
-  const int64_t scratch_bytes = ws_bytes - kStatusBytes;
   if (p->algo == HMV_SPLIT_FFT)
     return fft_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);
   if (p->algo == HMV_NTT) return ntt_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);

@@ -81,6 +81,14 @@ int oneshot_planned(int kind, const uint64_t* h, const uint64_t* x, uint64_t* y,
 // status block (a one-shot call's planning flags)
 int plan_matvec_impl(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, void* ws,
                      int64_t ws_bytes, hipStream_t s, void* const* events, bool clear);
+// the same with the status block and the scratch given apart (the status
+// block of a call need not precede its scratch)
+struct DevStatus;
+int plan_matvec_parts(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
+                      char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* events,
+                      bool clear);
+// records a message for hmv_last_error and returns code
+int fail_with(int code, const char* msg);
 
 }  // namespace hmv
 

@@ -40,6 +40,7 @@ SIGNATURES = {
     "hmv_plan_h": (_c_int, [ctypes.POINTER(_vp), _c_int, _vp, _c_i64, _c_i32, _c_int, _vp, _c_i64,
                             _vp, _c_i64, _vp]),
     "hmv_plan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp]),
+    "hmv_plan_matvec_noalloc": (_c_int, [_vp, _vp, _vp, _vp, _vp]),
     "hmv_debug_force_variants": (_c_int, [_c_i32, _c_i32]),
     "hmv_debug_force_layout": (_c_int, [_c_i32, _c_i32]),
     "hmv_batch_launches": (_c_i32, [_vp, _c_i32]),
@@ -229,6 +230,15 @@ class Plan:
                                    _stream(stream))
         if check:
             _check(rc, "plan_matvec")
+        return rc
+
+    def matvec_noalloc(self, x, y, status=None, stream=None, check=True) -> int:
+        """Planned matvec on the library's fixed scratch (allocates nothing);
+        status: optional 256-byte device buffer for read_status."""
+        rc = lib().hmv_plan_matvec_noalloc(self.handle, _ptr(x), _ptr(y), _ptr(status),
+                                           _stream(stream))
+        if check:
+            _check(rc, "plan_matvec_noalloc")
         return rc
 
     def matvec_events(self, x, y, events, ws=None, stream=None) -> int:
