@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--no-paths", action="store_true", help="skip the n=1024 four-path section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch section")
     ap.add_argument("--no-serving", action="store_true", help="skip the scheduler section")
+    ap.add_argument("--multi", default="2,4,8",
+                    help="block sizes k of the multi-vector section (Y = A [x_1..x_k]); "
+                         "empty = skip")
     ap.add_argument("--serving-sessions", type=int, default=24)
     ap.add_argument("--serving-loads", default="0.7",
                     help="comma-separated offered loads, as fractions of saturated throughput")
@@ -325,6 +328,9 @@ def main():
         "verify": verify, "cpu_baseline": cpu,
         "ntt_peer": None if (args.no_peer or args.algo != "split_fft")
         else section_peer(dev, plan, h_dev, xs, ys, n, P, W, K, Wm),
+        "multi_vector": None if (not args.multi or args.algo != "split_fft")
+        else section_multi(plan, xs, ys, n, W, info, [int(k) for k in args.multi.split(",")],
+                           K),
         "paths_n1024": None if args.no_paths else section_paths(dev),
         "batch": None if args.no_batch else section_batch(dev),
         "serving": None if args.no_serving else section_serving(dev, procs, args),
@@ -374,6 +380,61 @@ def section_peer(dev, fplan, h_dev, xs, ys, n, P, W, K, Wm):
     plan.close()
     if not same:
         raise SystemExit("NTT and split-FFT sessions disagree")
+    return res
+
+
+def section_multi(plan, xs, ys, n, W, info, ks, K):
+    """Blocks of k session vectors with the one plan (Y = A [x_1 .. x_k]):
+    matvecs/s, per-pass times per block, the index-axis pass's algorithmic
+    bytes per matvec (spectra of x and y per vector, the resident spectrum
+    once per block), and equality with the single-vector outputs."""
+    import torch
+
+    V = xs.shape[0]
+    Vf = min(V, K)               # vectors whose single-vector outputs ys holds
+    res = {}
+    kb = kernel_bytes("split_fft", n, W, info)
+    row = info["spectrum_cols"] * 16
+    h_bytes = kb[1] - 2 * n * row
+    for k in ks:
+        if k < 1 or k > Vf:
+            continue
+        ws = plan.multi_workspace(k)
+        nb = max(4, K // (2 * k))
+        blocks = [(j * k) % (Vf - k + 1) for j in range(nb)]
+        flat_x = xs.reshape(V * n, W)
+        yb = torch.zeros((k * n, W), dtype=torch.int64, device=xs.device)
+        for j in range(2):
+            b0 = blocks[j]
+            plan.matvec_multi(flat_x[b0 * n:(b0 + k) * n], yb, k, ws)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(nb)]
+        for r in evs:
+            for e in r:
+                e.record()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j, b0 in enumerate(blocks):
+            plan.matvec_multi(flat_x[b0 * n:(b0 + k) * n], yb, k, ws, events=evs[j])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        b0 = blocks[-1]
+        same = bool(torch.equal(yb.reshape(k, n, W), ys[b0:b0 + k]))
+        per = [statistics.mean(evs[j][q].elapsed_time(evs[j][q + 1]) for j in range(nb))
+               for q in range(3)]
+        cols_bytes = 2 * n * row + h_bytes / k          # per matvec
+        res[str(k)] = {
+            "matvecs_per_s": round(nb * k / wall, 1),
+            "ms_per_block": round(1000.0 * wall / nb, 4),
+            "kernels_ms_per_matvec": {nm: round(t / k, 4) for nm, t in
+                                      zip(kernel_names("split_fft", info), per)},
+            "cols_pass_alg_bytes_per_matvec": int(cols_bytes),
+            "cols_pass_GB_s": round(cols_bytes * k / (per[1] * 1e-3) / 1e9, 1),
+            "equal_to_single": same}
+        log(f"multi k={k}: {res[str(k)]}")
+        if not same:
+            raise SystemExit("block product differs from the single-vector products")
+        del ws
     return res
 
 

@@ -140,6 +140,22 @@ int hmv_plan_matvec(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* 
 int hmv_plan_matvec_events(const hmv_plan* plan, const uint64_t* x, uint64_t* y, void* ws,
                            int64_t ws_bytes, void* stream, void* const* events);
 int64_t hmv_plan_workspace_bytes(const hmv_plan* plan);
+/* A block of k vectors with the same plan, Y = A [x_1 .. x_k] (the repeated
+ * products with one fixed matrix of Section 1, several at a time: block
+ * Lanczos, or independent sessions on one matrix).  x and y hold k n
+ * numbers each, vector after vector ([k][n][W] words); 1 <= k <=
+ * HMV_MAX_VECTORS.  ws must hold hmv_plan_multi_workspace_bytes(plan, k)
+ * bytes (status block first).  Split-FFT plans run every pass once for the
+ * whole block and read the resident transform of h about once per block
+ * instead of once per vector; NTT and Karatsuba plans run the k products one
+ * after another on one workspace.  Every output equals hmv_plan_matvec of
+ * its vector.  events: NULL, or 4 events as in hmv_plan_matvec_events,
+ * recorded around the block's passes (the first product's for the other
+ * paths).  Asynchronous on `stream`.                                        */
+#define HMV_MAX_VECTORS 64
+int64_t hmv_plan_multi_workspace_bytes(const hmv_plan* plan, int32_t k);
+int hmv_plan_matvec_multi(const hmv_plan* plan, int32_t k, const uint64_t* x, uint64_t* y,
+                          void* ws, int64_t ws_bytes, void* stream, void* const* events);
 /* Launch tuning of the split-FFT path (on by default).  When on, planning a
  * shape (n, P, limb width) for the first time in the process also times
  * each launch variant of the index-axis pass (radix-16 or radix-8 register

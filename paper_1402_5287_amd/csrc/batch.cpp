@@ -146,7 +146,7 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
     b.logNt = z.logNt;
     b.C = z.C;
     b.gather = pr.kind == HMV_CIRCULANT ? (int)pr.n : 0;
-    b.reverse = pr.kind == HMV_HANKEL ? 0 : 1;
+    b.reverse = pr.kind == HMV_HANKEL ? 0 : (int)pr.n;   // reversal block: the n rows
     b.scale = z.z3 ? std::ldexp(1.0 / 3.0, -(z.logNt + z.logM))
                    : std::ldexp(1.0, -(z.logNt + z.logM + 1));
   }

@@ -106,6 +106,16 @@ __device__ __forceinline__ int64_t tile_index(int k, int row, int rows) {
   return ((int64_t)(k >> 3) * rows + row) * 8 + (k & 7);
 }
 
+// Output row of spectrum row i: with rev_block = 0 the same row, otherwise
+// reversed within its block of rev_block rows (the Toeplitz and circulant
+// outputs of one vector are its Hankel rows in reverse order; a block of
+// vectors stacks them).
+__device__ __forceinline__ int out_row(int i, int rev_block) {
+  if (rev_block <= 0) return i;
+  const int q = i / rev_block;
+  return q * rev_block + (rev_block - 1 - (i - q * rev_block));
+}
+
 __device__ __forceinline__ int gather_row(int r, int gather_n) {
   if (gather_n <= 0) return r;
   int s = (gather_n - 1 - r) % gather_n;
@@ -350,22 +360,34 @@ __device__ __forceinline__ void packed_product(double2* v, double2* buf, const d
 // threads and at most 128 VGPRs so that four waves fit per SIMD; the radix-8
 // form reloads the column for the odd half instead of keeping it), and the
 // column order (XCD-grouped or linear).
+//
+// A block of kvec vectors (spectrum rows v n .. v n + n - 1 of X1 and Y1 for
+// vector v) runs as kvec work-groups per column.  The kvec work-groups of a
+// column take consecutive dispatch slots of one XCD, so they run side by
+// side and read the same resident column through one L2: the spectrum of h
+// crosses HBM about once per column instead of once per vector.
 template <int LOGNH, int R>
 __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
     const double2* __restrict__ X1, const double2* __restrict__ Hh, int n, int C, int linear,
-    int pack, double2* __restrict__ Y1) {
+    int pack, int kvec, double2* __restrict__ Y1) {
   extern __shared__ double2 buf[];
-  const int c = linear ? (int)blockIdx.x : xcd_slot(blockIdx.x, gridDim.x);
+  // block b: vector (b / 8) mod kvec, column slot 8 ((b / 8) / kvec) + b mod 8
+  const int bq = (int)blockIdx.x >> 3;
+  const int vec = bq % kvec;
+  const int bc = ((bq / kvec) << 3) | ((int)blockIdx.x & 7);
+  const int c = linear ? bc : xcd_slot(bc, (int)gridDim.x / kvec);
   if (c >= C) return;
   constexpr int logNt = LOGNH + 1, Nh = 1 << LOGNH;
   constexpr int Ta = Nh >= R ? Nh / R : 1, per = Nh >= R ? R : Nh;
   constexpr int rs = kRealTwN >> logNt;
   const int t = threadIdx.x;
   const bool act = t < Ta;
-  const double2* xcol = X1 + tidx<kX1Tile>(c, 0, n);   // bin column of x, stride kX1Tile
+  const int rows = kvec * n;
+  // bin column of x, stride kX1Tile
+  const double2* xcol = X1 + tidx<kX1Tile>(c, vec * n, rows);
   const double2* he = Hh + (int64_t)c * (2 * Nh);
   const double2* ho = he + Nh;
-  double2* ycol = Y1 + tidx<kY1Tile>(c, 0, n);
+  double2* ycol = Y1 + tidx<kY1Tile>(c, vec * n, rows);
   // Every per-element loop sits in one guarded block with in-bounds
   // (clamped) addresses, so its loads are issued together rather than one
   // round trip per element.  With R = 16 the column is read from HBM once:
@@ -508,7 +530,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
   }
   row_status_publish(&rst, maxerr, bad, st);
   int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
-  const int row = out_reverse ? (n - 1 - i) : i;
+  const int row = out_row(i, out_reverse);
   carry_round_pack_fit(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
@@ -599,8 +621,9 @@ __global__ void __launch_bounds__(256) k_rows_fwd3(const uint64_t* __restrict__ 
   row_fwd3<LOGK, kX1Tile>(in, W, P, w, L, gather_n, out, rows_alloc, r, pack, buf, red, st);
 }
 
-// One row of the inverse pass (spectrum row i of Y1 in tiles of TW columns,
-// output row i, or n-1-i with out_reverse); blockDim.x = rows3_threads(K).
+// One row of the inverse pass (spectrum row i of the n rows of Y1 in tiles
+// of TW columns; output row out_row(i, out_reverse)); blockDim.x =
+// rows3_threads(K).
 template <int LOGK, int TW>
 __device__ __forceinline__ void row_inv3(const double2* __restrict__ Y1, int n, int L, int w,
                                          int P, int W, int out_reverse, int carry_off, int pack,
@@ -703,7 +726,7 @@ __device__ __forceinline__ void row_inv3(const double2* __restrict__ Y1, int n, 
   }
   row_status_publish(&rst, maxerr, bad, st);
   int64_t* cs = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(buf) + carry_off);
-  const int row = out_reverse ? (n - 1 - i) : i;
+  const int row = out_row(i, out_reverse);
   carry_round_pack_fit(coef, NC, w, P, W, cs, y + (int64_t)row * W, red);
 }
 
@@ -824,13 +847,13 @@ hipError_t cols_plan_t(const double2* H1, int rows, int C, double scale, int pac
 
 template <int LOGNH, int R>
 hipError_t cols_pass_r(const double2* X1, const double2* Hh, int n, int C, int linear, int pack,
-                       double2* Y1, hipStream_t s) {
+                       int kvec, double2* Y1, hipStream_t s) {
   const size_t lds = sizeof(double2) * (size_t)lds_points(1 << LOGNH);
   hipError_t e = set_lds((const void*)k_cols_pass<LOGNH, R>, lds);
   if (e != hipSuccess) return e;
-  const int grid = (C + 7) / 8 * 8;
+  const int grid = (C + 7) / 8 * 8 * kvec;    // xcd_slot needs a multiple of 8 per vector
   hipLaunchKernelGGL((k_cols_pass<LOGNH, R>), dim3(grid), dim3(fft_threads(1 << LOGNH, R)), lds,
-                     s, X1, Hh, n, C, linear, pack, Y1);
+                     s, X1, Hh, n, C, linear, pack, kvec, Y1);
   return hipGetLastError();
 }
 
@@ -838,12 +861,12 @@ hipError_t cols_pass_r(const double2* X1, const double2* Hh, int n, int C, int l
 // column order
 template <int LOGNH>
 hipError_t cols_pass_t(const double2* X1, const double2* Hh, int n, int C, int variant, int pack,
-                       double2* Y1, hipStream_t s) {
+                       int kvec, double2* Y1, hipStream_t s) {
   const int linear = (variant >> 1) & 1;
   if constexpr (has_radix8(LOGNH)) {
-    if (variant & 1) return cols_pass_r<LOGNH, 8>(X1, Hh, n, C, linear, pack, Y1, s);
+    if (variant & 1) return cols_pass_r<LOGNH, 8>(X1, Hh, n, C, linear, pack, kvec, Y1, s);
   }
-  return cols_pass_r<LOGNH, 16>(X1, Hh, n, C, linear, pack, Y1, s);
+  return cols_pass_r<LOGNH, 16>(X1, Hh, n, C, linear, pack, kvec, Y1, s);
 }
 
 #define HMV_NT_DISPATCH(FN, ...)                  \
@@ -870,8 +893,9 @@ hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, doubl
 }
 
 hipError_t launch_cols_pass(const double2* X1, const double2* Hh, int n, int C, int logNt,
-                            int pack, double2* Y1, int variant, hipStream_t s) {
-  HMV_NT_DISPATCH(cols_pass_t, X1, Hh, n, C, variant, pack, Y1, s)
+                            int pack, double2* Y1, int variant, hipStream_t s, int kvec) {
+  if (kvec < 1) return hipErrorInvalidValue;
+  HMV_NT_DISPATCH(cols_pass_t, X1, Hh, n, C, variant, pack, kvec, Y1, s)
 }
 
 template <int LOGM, int R>

@@ -44,8 +44,11 @@ hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, doubl
 // variant bit 0: radix-8 register transforms (where they exist, 8^k points);
 // bit 1 (column pass only): linear instead of XCD-grouped column order.
 constexpr int kColsVariants = 4, kRowsInvVariants = 2;
+// kvec vectors: X1 and Y1 hold kvec n rows, vector v in rows v n .. v n + n - 1
 hipError_t launch_cols_pass(const double2* X1, const double2* Hh, int n, int C, int logNt,
-                            int pack, double2* Y1, int variant, hipStream_t s);
+                            int pack, double2* Y1, int variant, hipStream_t s, int kvec = 1);
+// inverse row passes: n rows of Y1; out_reverse = 0 writes spectrum row i to
+// output row i, out_reverse = m > 0 reverses the rows within each block of m
 hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
                            int out_reverse, int pack, uint64_t* y, DevStatus* st, int variant,
                            hipStream_t s);

@@ -292,27 +292,41 @@ hipError_t mark(void* const* ev, int k, hipStream_t s) {
   return hipEventRecord(static_cast<hipEvent_t>(ev[k]), s);
 }
 
+// Workspace after the status block for a block of kvec vectors: the row
+// spectra of x and of y, kvec n rows each.
+int64_t fft_mv_scratch(const hmv_plan* p, int kvec) {
+  return 2 * align_up(16 * 8 * int64_t(p->tiles) * p->n * kvec);
+}
+
+// kvec vectors at once (x and y hold kvec n numbers, vector after vector):
+// each row pass covers all kvec n rows in one launch, and the index-axis
+// pass reads each resident column once for the kvec vectors (its kvec
+// work-groups of a column share one L2).
 int fft_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
-                    char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* ev) {
-  if (scratch_bytes < p->mv_scratch) return HMV_ENOMEM;
-  const int n = (int)p->n;
+                    char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* ev,
+                    int kvec = 1) {
+  const int64_t need = fft_mv_scratch(p, kvec);
+  if (scratch_bytes < need) return HMV_ENOMEM;
+  const int n = (int)p->n, rows = (int)(p->n * kvec);
   const int W = (int)words_of(p->P);
   double2* X1 = reinterpret_cast<double2*>(scratch);
-  double2* Y1 = reinterpret_cast<double2*>(scratch + p->mv_scratch / 2);
+  double2* Y1 = reinterpret_cast<double2*>(scratch + need / 2);
   hipError_t e = mark(ev, 0, s);
   if (e == hipSuccess)
-    e = p->z3 ? launch_rows_fwd3(x, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, p->pack, st, s)
-              : launch_rows_fwd(x, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, p->pack, st, s);
+    e = p->z3
+            ? launch_rows_fwd3(x, W, p->P, p->w, p->L, rows, 0, p->logM, X1, rows, p->pack, st, s)
+            : launch_rows_fwd(x, W, p->P, p->w, p->L, rows, 0, p->logM, X1, rows, p->pack, st, s);
   if (e != hipSuccess) return status_from_hip(e, "rows fwd (x)");
   e = mark(ev, 1, s);
   if (e == hipSuccess)
-    e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, p->pack, Y1, p->cols_variant, s);
+    e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, p->pack, Y1, p->cols_variant, s, kvec);
   if (e != hipSuccess) return status_from_hip(e, "cols pass");
-  const int rev = (p->kind == HMV_HANKEL) ? 0 : 1;
+  // Toeplitz and circulant outputs: each vector's rows reversed
+  const int rev = (p->kind == HMV_HANKEL) ? 0 : n;
   e = mark(ev, 2, s);
   if (e == hipSuccess)
-    e = p->z3 ? launch_rows_inv3(Y1, n, p->logM, p->L, p->w, p->P, W, rev, p->pack, y, st, s)
-              : launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, rev, p->pack, y, st,
+    e = p->z3 ? launch_rows_inv3(Y1, rows, p->logM, p->L, p->w, p->P, W, rev, p->pack, y, st, s)
+              : launch_rows_inv(Y1, rows, p->logM, p->L, p->w, p->P, W, rev, p->pack, y, st,
                                 p->rows_inv_variant, s);
   if (e == hipSuccess) e = mark(ev, 3, s);
   return status_from_hip(e, "rows inv");
@@ -790,9 +804,47 @@ int plan_matvec_parts(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, DevSt
   return HMV_EUNSUPPORTED;
 }
 
+int plan_matvec_multi_impl(const ::hmv_plan* p, int32_t k, const uint64_t* x, uint64_t* y,
+                           void* ws, int64_t ws_bytes, hipStream_t s, void* const* events) {
+  if (!p || !x || !y || !ws) return HMV_EINVAL;
+  if (k < 1 || k > HMV_MAX_VECTORS) return HMV_EINVAL;
+  if (ws_bytes < kStatusBytes) return HMV_ENOMEM;
+  clear_stale_error();
+  DevStatus* st = static_cast<DevStatus*>(ws);
+  char* scratch = static_cast<char*>(ws) + kStatusBytes;
+  const int64_t scratch_bytes = ws_bytes - kStatusBytes;
+  if (p->algo == HMV_SPLIT_FFT) {
+    if (scratch_bytes < fft_mv_scratch(p, k)) return HMV_ENOMEM;
+    hipError_t e = launch_clear_status(st, s);
+    if (e != hipSuccess) return status_from_hip(e, "clear status");
+    return fft_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events, k);
+  }
+  // the exact paths: one product after another on the same workspace
+  if (scratch_bytes < p->mv_scratch) return HMV_ENOMEM;
+  const int64_t stride = p->n * words_of(p->P);
+  for (int32_t v = 0; v < k; ++v) {
+    const int rc = plan_matvec_parts(p, x + v * stride, y + v * stride, st, scratch,
+                                     scratch_bytes, s, v == 0 ? events : nullptr, v == 0);
+    if (rc != HMV_OK) return rc;
+  }
+  return HMV_OK;
+}
+
 }  // namespace hmv
 
 extern "C" {
+
+int64_t hmv_plan_multi_workspace_bytes(const hmv_plan* p, int32_t k) {
+  if (!p || k < 1 || k > HMV_MAX_VECTORS) return HMV_EINVAL;
+  if (p->algo == HMV_SPLIT_FFT) return kStatusBytes + fft_mv_scratch(p, k);
+  return kStatusBytes + p->mv_scratch;
+}
+
+int hmv_plan_matvec_multi(const hmv_plan* p, int32_t k, const uint64_t* x, uint64_t* y,
+                          void* ws, int64_t ws_bytes, void* stream, void* const* events) {
+  return hmv::plan_matvec_multi_impl(p, k, x, y, ws, ws_bytes, static_cast<hipStream_t>(stream),
+                                     events);
+}
 
 int64_t hmv_plan_workspace_bytes(const hmv_plan* p) {
   if (!p) return HMV_EINVAL;

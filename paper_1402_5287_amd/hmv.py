@@ -41,6 +41,9 @@ SIGNATURES = {
                             _vp, _c_i64, _vp]),
     "hmv_plan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp]),
     "hmv_plan_matvec_noalloc": (_c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "hmv_plan_multi_workspace_bytes": (_c_i64, [_vp, _c_i32]),
+    "hmv_plan_matvec_multi": (_c_int, [_vp, _c_i32, _vp, _vp, _vp, _c_i64, _vp,
+                                       ctypes.POINTER(_vp)]),
     "hmv_debug_force_variants": (_c_int, [_c_i32, _c_i32]),
     "hmv_debug_force_layout": (_c_int, [_c_i32, _c_i32]),
     "hmv_batch_launches": (_c_i32, [_vp, _c_i32]),
@@ -230,6 +233,25 @@ class Plan:
                                    _stream(stream))
         if check:
             _check(rc, "plan_matvec")
+        return rc
+
+    def multi_workspace(self, k: int):
+        b = lib().hmv_plan_multi_workspace_bytes(self.handle, int(k))
+        if b < 0:
+            raise HmvError(int(b), "hmv_plan_multi_workspace_bytes")
+        return workspace(int(b), device=self.mem.device)
+
+    def matvec_multi(self, x, y, k: int, ws, events=None, stream=None, check=True) -> int:
+        """Y = A [x_1 .. x_k]: x, y hold k n numbers, vector after vector."""
+        arr = None
+        if events is not None:
+            arr = (_vp * 4)()
+            for j, ev in enumerate(events):
+                arr[j] = ctypes.c_void_p(ev.cuda_event) if ev is not None else None
+        rc = lib().hmv_plan_matvec_multi(self.handle, int(k), _ptr(x), _ptr(y), _ptr(ws),
+                                         ws.numel(), _stream(stream), arr)
+        if check:
+            _check(rc, "plan_matvec_multi")
         return rc
 
     def matvec_noalloc(self, x, y, status=None, stream=None, check=True) -> int:
