@@ -168,6 +168,41 @@ int hmv_autotune(int32_t on);
 int hmv_plan_info(const hmv_plan* plan, hmv_plan_info_t* info);
 int hmv_plan_destroy(hmv_plan* plan);
 
+/* ---------------------------------------------------------------- floating point
+ * Multiprecision floating-point numbers (Section 2: a mantissa of b bits;
+ * Section 3: a = B_0 sum_k B^k a_k, with a per-number factor B_0).  A number
+ * is a significand M with |M| < 2^P, stored as hmv_words(P) words in two's
+ * complement like the fixed-point numbers, and an int32 exponent e (a
+ * separate device array): value M 2^(e-P).  y = A x is the exact sum
+ * rounded once to P significant bits, to nearest with ties to even (as
+ * MPFR's round-to-nearest); outputs are normalised, 2^(P-1) <= |M| < 2^P,
+ * or zero with exponent 0.  Output exponents must fit in int32 (else the
+ * overflow flag, HMV_EBOUND from hmv_read_status).
+ *
+ * `spread` is the widest exponent range the plan admits within h and within
+ * each x (over nonzero entries): entries are aligned to their operand's
+ * largest exponent as fixed-point integers of Q = P + spread fractional bits
+ * (Q <= HMV_MAX_P), a fixed-point plan at Q holds the transform of h, and
+ * its carry step keeps the exact sums, which are then rounded.  h wider
+ * than spread, or a significand needing more than P bits, fails
+ * hmv_fplan_h with HMV_ERANGE (it synchronises `stream` once, to read the
+ * exponent range of h); such an x flags the range error on the device
+ * (HMV_ERANGE from hmv_read_status on ws), and its y is unspecified.
+ * Sizes: hmv_fplan_bytes (plan memory), hmv_fplan_workspace_bytes (ws of
+ * both calls; its first 256 bytes receive the status).  x_exp, h_exp and
+ * y_exp are device arrays of int32.  hmv_fplan_info reports the inner
+ * fixed-point plan, Q and the largest exponent of h.                      */
+typedef struct hmv_fplan hmv_fplan;
+int64_t hmv_fplan_bytes(int kind, int64_t n, int32_t P, int32_t spread);
+int64_t hmv_fplan_workspace_bytes(int kind, int64_t n, int32_t P, int32_t spread);
+int hmv_fplan_h(hmv_fplan** out, int kind, const uint64_t* h_sig, const int32_t* h_exp,
+                int64_t n, int32_t P, int32_t spread, void* plan_mem, int64_t plan_bytes,
+                void* ws, int64_t ws_bytes, void* stream);
+int hmv_fplan_matvec(const hmv_fplan* plan, const uint64_t* x_sig, const int32_t* x_exp,
+                     uint64_t* y_sig, int32_t* y_exp, void* ws, int64_t ws_bytes, void* stream);
+int hmv_fplan_info(const hmv_fplan* plan, hmv_plan_info_t* info, int32_t* Q, int32_t* Eh);
+int hmv_fplan_destroy(hmv_fplan* plan);
+
 /* ---------------------------------------------------------------- no allocation
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Same

@@ -326,6 +326,8 @@ __host__ __device__ inline int carry_lds_bytes(int T) { return 8 * T + 64; }
 // Then the round bit (P-1), the sticky OR below it and bit P decide the
 // round-half-even increment of floor(S / 2^P), whose words are cut from the
 // limbs; the increment ripples through the lowest all-ones words.
+// P = 0 asks for S itself, unrounded: its W low words (the caller sizes W
+// for the whole sum; the floating-point interface keeps exact sums).
 // Limbs a thread keeps in registers during the carry passes; a longer chunk
 // (only for very large P at small widths) runs the same passes from LDS.
 constexpr int kCarryRegs = 32;
@@ -406,7 +408,9 @@ __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, i
   const uint32_t pre = block_exclusive_scan(g, kWordIdent, WordOp(), red);
   const int kap = (int)((pre >> 2) & 3u) - 1;      // the map applied to kappa_0 = 0
   // 3. incoming carry; sticky bit (any 1 below bit P-1) from the final limbs
-  const int ep = (P - 1) / w, rp = (P - 1) - ep * w;
+  //    (no rounding with P = 0: ep = -1 leaves no limb below the round bit)
+  const bool exact = P <= 0;
+  const int ep = exact ? -1 : (P - 1) / w, rp = exact ? 0 : (P - 1) - ep * w;
   const int64_t rpmask = (int64_t(1) << rp) - 1;
   int64_t carry = cin + kap;
   int st = 0;
@@ -440,9 +444,9 @@ __device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, i
   const int sticky = __syncthreads_or(st);
   const int64_t top = cs[T];
   const int64_t ncw = (int64_t)NC * w;             // > P: every bit below P+1 is in a limb
-  const int rbit = (int)((coef[ep] >> rp) & 1);
-  const int el = P / w;
-  const int lsb = (int)((coef[el] >> (P - el * w)) & 1);
+  const int rbit = exact ? 0 : (int)((coef[ep] >> rp) & 1);
+  const int el = exact ? 0 : P / w;
+  const int lsb = exact ? 0 : (int)((coef[el] >> (P - el * w)) & 1);
   const int up = rbit && (sticky || lsb);
   // words of floor(S / 2^P): bits [P + 64 m, P + 64 m + 64) of S; for
   // w >= 8 at most 64 / w + 2 <= 10 limbs overlap a word

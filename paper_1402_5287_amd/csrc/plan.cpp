@@ -302,13 +302,16 @@ int64_t fft_mv_scratch(const hmv_plan* p, int kvec) {
 // each row pass covers all kvec n rows in one launch, and the index-axis
 // pass reads each resident column once for the kvec vectors (its kvec
 // work-groups of a column share one L2).
+// exact_words > 0: each output is the exact sum S_i, unrounded, in
+// exact_words words (the carry step with P = 0) instead of y_i.
 int fft_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
                     char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* ev,
-                    int kvec = 1) {
+                    int kvec = 1, int exact_words = 0) {
   const int64_t need = fft_mv_scratch(p, kvec);
   if (scratch_bytes < need) return HMV_ENOMEM;
   const int n = (int)p->n, rows = (int)(p->n * kvec);
   const int W = (int)words_of(p->P);
+  const int Pout = exact_words > 0 ? 0 : p->P, Wout = exact_words > 0 ? exact_words : W;
   double2* X1 = reinterpret_cast<double2*>(scratch);
   double2* Y1 = reinterpret_cast<double2*>(scratch + need / 2);
   hipError_t e = mark(ev, 0, s);
@@ -325,8 +328,9 @@ int fft_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus
   const int rev = (p->kind == HMV_HANKEL) ? 0 : n;
   e = mark(ev, 2, s);
   if (e == hipSuccess)
-    e = p->z3 ? launch_rows_inv3(Y1, rows, p->logM, p->L, p->w, p->P, W, rev, p->pack, y, st, s)
-              : launch_rows_inv(Y1, rows, p->logM, p->L, p->w, p->P, W, rev, p->pack, y, st,
+    e = p->z3 ? launch_rows_inv3(Y1, rows, p->logM, p->L, p->w, Pout, Wout, rev, p->pack, y, st,
+                                 s)
+              : launch_rows_inv(Y1, rows, p->logM, p->L, p->w, Pout, Wout, rev, p->pack, y, st,
                                 p->rows_inv_variant, s);
   if (e == hipSuccess) e = mark(ev, 3, s);
   return status_from_hip(e, "rows inv");
@@ -393,9 +397,11 @@ int ntt_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
 }
 
 int ntt_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
-                    char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* ev) {
+                    char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* ev,
+                    int exact_words = 0) {
   if (scratch_bytes < p->mv_scratch) return HMV_ENOMEM;
   const int n = (int)p->n, W = (int)words_of(p->P);
+  const int Pout = exact_words > 0 ? 0 : p->P, Wout = exact_words > 0 ? exact_words : W;
   uint64_t* X1 = reinterpret_cast<uint64_t*>(scratch);
   uint64_t* Y1 = reinterpret_cast<uint64_t*>(scratch + p->mv_scratch / 2);
   hipError_t e = mark(ev, 0, s);
@@ -408,7 +414,7 @@ int ntt_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus
   const int rev = (p->kind == HMV_HANKEL) ? 0 : 1;
   e = mark(ev, 2, s);
   if (e == hipSuccess)
-    e = launch_ntt_rows_inv(Y1, n, p->logNz, p->L, p->w, p->P, W, rev, kNttYLogT, y, st, s);
+    e = launch_ntt_rows_inv(Y1, n, p->logNz, p->L, p->w, Pout, Wout, rev, kNttYLogT, y, st, s);
   if (e == hipSuccess) e = mark(ev, 3, s);
   return status_from_hip(e, "ntt rows inv");
 }
@@ -789,7 +795,7 @@ int plan_matvec_impl(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, void* 
 
 int plan_matvec_parts(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
                       char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* events,
-                      bool clear) {
+                      bool clear, int exact_words) {
   if (!p || !x || !y || !st || !scratch) return HMV_EINVAL;
   clear_stale_error();
   if (clear) {
@@ -797,8 +803,10 @@ int plan_matvec_parts(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, DevSt
     if (e != hipSuccess) return status_from_hip(e, "clear status");
   }
   if (p->algo == HMV_SPLIT_FFT)
-    return fft_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);
-  if (p->algo == HMV_NTT) return ntt_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);
+    return fft_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events, 1, exact_words);
+  if (p->algo == HMV_NTT)
+    return ntt_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events, exact_words);
+  if (exact_words > 0) return HMV_EUNSUPPORTED;
   if (p->algo == HMV_KARATSUBA)
     return kara_plan_matvec(p, x, y, st, scratch, scratch_bytes, s, events);
   return HMV_EUNSUPPORTED;

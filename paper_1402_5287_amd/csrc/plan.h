@@ -84,9 +84,11 @@ int plan_matvec_impl(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, void* 
 // the same with the status block and the scratch given apart (the status
 // block of a call need not precede its scratch)
 struct DevStatus;
+// exact_words > 0 (split-FFT and NTT plans): y receives the exact sums S_i,
+// unrounded, exact_words words each, instead of the rounded y_i
 int plan_matvec_parts(const ::hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus* st,
                       char* scratch, int64_t scratch_bytes, hipStream_t s, void* const* events,
-                      bool clear);
+                      bool clear, int exact_words = 0);
 // records a message for hmv_last_error and returns code
 int fail_with(int code, const char* msg);
 

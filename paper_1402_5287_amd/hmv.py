@@ -41,6 +41,13 @@ SIGNATURES = {
                             _vp, _c_i64, _vp]),
     "hmv_plan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp]),
     "hmv_plan_matvec_noalloc": (_c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "hmv_fplan_bytes": (_c_i64, [_c_int, _c_i64, _c_i32, _c_i32]),
+    "hmv_fplan_workspace_bytes": (_c_i64, [_c_int, _c_i64, _c_i32, _c_i32]),
+    "hmv_fplan_h": (_c_int, [ctypes.POINTER(_vp), _c_int, _vp, _vp, _c_i64, _c_i32, _c_i32, _vp,
+                             _c_i64, _vp, _c_i64, _vp]),
+    "hmv_fplan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _c_i64, _vp]),
+    "hmv_fplan_info": (_c_int, [_vp, _vp, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32)]),
+    "hmv_fplan_destroy": (_c_int, [_vp]),
     "hmv_plan_multi_workspace_bytes": (_c_i64, [_vp, _c_i32]),
     "hmv_plan_matvec_multi": (_c_int, [_vp, _c_i32, _vp, _vp, _vp, _c_i64, _vp,
                                        ctypes.POINTER(_vp)]),
@@ -277,6 +284,57 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             lib().hmv_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FPlan:
+    """Floating-point plan (hmv_fplan_h): significands as (count, W) words,
+    exponents as int32 device tensors; matvec(x_sig, x_exp, y_sig, y_exp)."""
+
+    def __init__(self, kind, h_sig, h_exp, n: int, P: int, spread: int, stream=None):
+        import torch
+        self.kind = KINDS.get(kind, kind)
+        self.n, self.P, self.spread = int(n), int(P), int(spread)
+        dev = h_sig.device
+        pb = lib().hmv_fplan_bytes(self.kind, n, P, spread)
+        wb = lib().hmv_fplan_workspace_bytes(self.kind, n, P, spread)
+        if pb < 0 or wb < 0:
+            raise HmvError(int(min(pb, wb)), "fplan sizes")
+        self.mem = torch.empty(int(pb), dtype=torch.uint8, device=dev)
+        self.ws = torch.empty(int(wb), dtype=torch.uint8, device=dev)
+        handle = ctypes.c_void_p(0)
+        rc = lib().hmv_fplan_h(ctypes.byref(handle), self.kind, _ptr(h_sig), _ptr(h_exp), n, P,
+                               spread, _ptr(self.mem), self.mem.numel(), _ptr(self.ws),
+                               self.ws.numel(), _stream(stream))
+        _check(rc, "fplan_h")
+        self.handle = handle
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        Q, Eh = _c_i32(0), _c_i32(0)
+        _check(lib().hmv_fplan_info(self.handle, ctypes.byref(inf), ctypes.byref(Q),
+                                    ctypes.byref(Eh)), "fplan_info")
+        d = inf.as_dict()
+        d["Q"], d["Eh"] = int(Q.value), int(Eh.value)
+        return d
+
+    def matvec(self, x_sig, x_exp, y_sig, y_exp, ws=None, stream=None, check=True) -> int:
+        ws = self.ws if ws is None else ws
+        rc = lib().hmv_fplan_matvec(self.handle, _ptr(x_sig), _ptr(x_exp), _ptr(y_sig),
+                                    _ptr(y_exp), _ptr(ws), ws.numel(), _stream(stream))
+        if check:
+            _check(rc, "fplan_matvec")
+        return rc
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().hmv_fplan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
