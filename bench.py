@@ -93,6 +93,23 @@ def make_vectors(n, P, count, procs):
         return pool.map(_gen_x, [(n, P, k) for k in range(count)], chunksize=4)
 
 
+def host_cpu():
+    """nproc, the CPUs this process may use, and lscpu's model line."""
+    import subprocess
+    out = {"nproc": os.cpu_count(),
+           "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core",
+                             "CPU(s)"):
+                out[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return out
+
+
 def _oracle_rows(H, X, P, rows, procs):
     from oracle import hankel
     return hankel.matvec_rows("hankel", H, X, P, rows, processes=procs)
@@ -110,18 +127,20 @@ def main():
                     help="path of the timed session (the headline is split_fft)")
     ap.add_argument("--no-peer", action="store_true",
                     help="skip timing the NTT path on the same session")
-    ap.add_argument("--cpu-rows", type=int, default=16, help="oracle row sample (0 = skip)")
+    ap.add_argument("--cpu-rows", type=int, default=24,
+                    help="oracle row sample (0 = skip); 24 rows are about 30 s of CPU work")
     ap.add_argument("--no-school", action="store_true", help="skip the GPU schoolbook comparison")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-verify", action="store_true", help="skip the GMP full-vector check")
     ap.add_argument("--no-paths", action="store_true", help="skip the n=1024 four-path section")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch section")
     ap.add_argument("--no-serving", action="store_true", help="skip the scheduler section")
+    ap.add_argument("--no-lanczos", action="store_true", help="skip the Lanczos section")
     ap.add_argument("--multi", default="2,4,8",
                     help="block sizes k of the multi-vector section (Y = A [x_1..x_k]); "
                          "empty = skip")
     ap.add_argument("--serving-sessions", type=int, default=24)
-    ap.add_argument("--serving-loads", default="0.7",
+    ap.add_argument("--serving-loads", default="0.5,0.7,0.9",
                     help="comma-separated offered loads, as fractions of saturated throughput")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-pool-gb", type=float, default=4.5)
@@ -145,7 +164,9 @@ def main():
     W = hmv.words(P)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    procs = max(1, min(16, os.cpu_count() or 1))
+    # the host share of one GPU is 16 cores; use them all, never more
+    procs = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+                       else (os.cpu_count() or 1)))
 
     if args.copy_calibration > 0:
         a = torch.empty(args.copy_calibration // 8, dtype=torch.int64, device=dev)
@@ -304,8 +325,9 @@ def main():
         cpu = {"value": round((len(rows) / n) / cw, 6), "unit": "matvecs/s", "cores": procs,
                "kind": "oracle",
                "sample": f"{len(rows)} of {n} rows of one matvec (exact Python-int schoolbook, "
-                         f"{procs} processes, {cw:.1f} s wall), scaled by rows/n",
-               "rows_equal_gpu": same}
+                         f"{procs} processes, {cw:.1f} s wall, about {cw * procs:.0f} s of "
+                         f"CPU), scaled by rows/n (extrapolated)",
+               "host": host_cpu(), "rows_equal_gpu": same}
         log(f"cpu oracle: {cpu}")
         if not same:
             raise SystemExit("oracle rows differ from the GPU result")
@@ -331,6 +353,7 @@ def main():
         "multi_vector": None if (not args.multi or args.algo != "split_fft")
         else section_multi(plan, xs, ys, n, W, info, [int(k) for k in args.multi.split(",")],
                            K),
+        "lanczos": None if args.no_lanczos else section_lanczos(dev),
         "paths_n1024": None if args.no_paths else section_paths(dev),
         "batch": None if args.no_batch else section_batch(dev),
         "serving": None if args.no_serving else section_serving(dev, procs, args),
@@ -435,6 +458,45 @@ def section_multi(plan, xs, ys, n, W, info, ks, K):
         if not same:
             raise SystemExit("block product differs from the single-vector products")
         del ws
+    return res
+
+
+def section_lanczos(dev, steps=20):
+    """The Lanczos tridiagonalisation (hmv_lanczos) over planned matvecs at
+    the paper's Lanczos sizes (n = 100) and at n = 1024, P = 33220: time per
+    step, and the share of the matvec in it."""
+    import torch
+
+    import seeded_inputs as si
+    from paper_1402_5287_amd import hmv
+    res = {}
+    for n in (100, 1024):
+        P = 33220
+        h = si.uniform(2 * n - 1, P, (6, 0, n))
+        q1 = hmv.to_device(si.unit_norm(si.uniform(n, P, (6, 1, n)), P), dev)
+        plan = hmv.Plan("hankel", hmv.to_device(h, dev), n, P, algo="split_fft")
+        plan.lanczos(q1, 2)                                 # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        alpha, beta, done, _, ws = plan.lanczos(q1, steps)
+        e1.record()
+        torch.cuda.synchronize()
+        rc, flags, _ = hmv.read_status(ws)
+        ms = e0.elapsed_time(e1)
+        y = torch.zeros_like(q1)
+        m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        m0.record()
+        for _ in range(steps):
+            plan.matvec(q1, y)
+        m1.record()
+        torch.cuda.synchronize()
+        mv = m0.elapsed_time(m1) / steps
+        done_k = int(done.item())
+        res[str(n)] = {"P": P, "steps": done_k, "ms_per_step": round(ms / max(1, done_k), 3),
+                       "matvec_ms": round(mv, 4), "status": rc, "flags": flags}
+        log(f"lanczos n={n}: {res[str(n)]}")
+        plan.close()
     return res
 
 

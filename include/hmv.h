@@ -168,6 +168,32 @@ int hmv_autotune(int32_t on);
 int hmv_plan_info(const hmv_plan* plan, hmv_plan_info_t* info);
 int hmv_plan_destroy(hmv_plan* plan);
 
+/* ---------------------------------------------------------------- Lanczos
+ * Lanczos tridiagonalisation over a Hankel plan (Section 1: repeated
+ * products with one symmetric matrix reduce it to tridiagonal form, whose
+ * eigenvalues QR iterations then find), in P-bit fixed point.  Every scalar
+ * and entry is one rounding (nearest, ties to even, at 2^-P) of an exact
+ * expression; from q_1 (|entries| <= 1, normally unit 2-norm), beta_1 = 0:
+ *   w = A q_j (hmv_plan_matvec),  alpha_j = rne(q_j . w),
+ *   r_i = rne(w_i - alpha_j q_j,i - beta_j q_j-1,i),  nu = rne(r . r),
+ *   stop (beta_j+1 = 0) when nu < 2^-120, else rho = 1/sqrt(nu) by the
+ *   fixed Newton iteration y <- y (3 - mu y^2) / 2 on mu = nu 4^-s in
+ *   [1/4, 1) from y = 3/2, bitlen(P) + 6 steps, each product rounded, then
+ *   rho = y 2^-s; beta_j+1 = rne(nu rho), q_j+1,i = rne(r_i rho) clamped to
+ *   [-1, 1].
+ * Runs `steps` steps asynchronously on `stream` with no host round trip.
+ * alpha, beta: device arrays of `steps` numbers (hmv_words(P) words each):
+ * alpha_1.., beta_2..; after a stop at step j, beta_j+1 = 0 and later
+ * entries are left untouched.  *steps_done (device int32) receives the
+ * number of alphas computed.  basis: NULL, or a device array of steps x n
+ * numbers that receives q_1, q_2, ....  ws: hmv_lanczos_workspace_bytes
+ * (status block first: matvec range errors show in hmv_read_status).
+ * Hankel plans only (the matrix must be symmetric); any algorithm.        */
+int64_t hmv_lanczos_workspace_bytes(const hmv_plan* plan);
+int hmv_lanczos(const hmv_plan* plan, const uint64_t* q1, int32_t steps, uint64_t* alpha,
+                uint64_t* beta, int32_t* steps_done, uint64_t* basis, void* ws, int64_t ws_bytes,
+                void* stream);
+
 /* ---------------------------------------------------------------- floating point
  * Multiprecision floating-point numbers (Section 2: a mantissa of b bits;
  * Section 3: a = B_0 sum_k B^k a_k, with a per-number factor B_0).  A number

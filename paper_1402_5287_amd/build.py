@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libhmv.so")
 
 SOURCES = ["api.cpp", "plan.cpp", "tables.cpp", "status.hip", "school.hip", "fftpath.hip",
            "nttpath.hip", "batch.cpp",
-           "serve.cpp", "noalloc.hip", "floatio.hip"]
+           "serve.cpp", "noalloc.hip", "floatio.hip", "lanczos.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

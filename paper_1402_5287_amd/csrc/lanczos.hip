@@ -1,0 +1,483 @@
+// Lanczos tridiagonalisation over planned matvecs (Section 1: the Lanczos
+// iteration multiplies one symmetric matrix by a sequence of vectors and
+// reduces it to a tridiagonal matrix whose eigenvalues QR iterations find).
+//
+// Fixed point with P fractional bits throughout; every scalar and entry is
+// one rounding (to nearest, ties to even, at 2^-P) of an exact expression:
+//   w       = A q_j                                    (planned matvec)
+//   alpha_j = rne(sum_i q_j,i w_i)
+//   r_i     = rne(w_i - alpha_j q_j,i - beta_j q_j-1,i)
+//   nu      = rne(sum_i r_i^2); stop when nu < 2^-120
+//   rho     = 1/sqrt(nu) by a fixed Newton iteration on mu = nu 4^-s in
+//             [1/4, 1):  y <- rne(rne(3 y 2^P - y rne(mu rne(y y))) / 2),
+//             y_0 = 3/2, bitlen(P) + 6 steps, then rho = y 2^-s
+//   beta_j+1 = rne(nu rho),   q_j+1,i = rne(r_i rho) clamped to [-1, 1]
+//
+// The exact expressions are big-integer sums of products.  A work-group
+// holds each operand's magnitude as 32-bit limbs in LDS and sums the limb
+// products column by column (the low and high halves of every 64-bit limb
+// product in their own columns, signed int64 column sums); the shared
+// carry / round / pack step (limb width 32) then turns the column sums into
+// the rounded result.  Dot products sum the columns of many entries per
+// work-group and then across work-groups.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdio>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "hmv.h"
+#include "kernels.h"
+#include "plan.h"
+
+namespace hmv {
+namespace {
+
+constexpr int kLzThreads = 256;
+constexpr int kLzLimbs = 2 * kMaxWords;              // 32-bit limbs of one number
+constexpr int kLzCols = (4 * kMaxWords + 2 + kLzThreads - 1) / kLzThreads;   // columns per thread
+constexpr int kLzMaxNC = kLzCols * kLzThreads;
+constexpr int kStopBytes = 256;                       // stop flag and step count
+
+struct LzShared {
+  uint64_t wbuf[kMaxWords];                           // words of the number being loaded
+  uint32_t mag[5][kLzLimbs];                          // magnitudes (32-bit limbs)
+  int64_t coef[kLzMaxNC + 2];                         // column sums
+  int64_t cs[kLzThreads + 8];                         // carry scratch (carry_lds_bytes)
+  uint64_t out[kMaxWords];                            // a rounded result
+  uint32_t red[32];
+  int first_nz;
+};
+
+// Loads W two's complement words and stores the magnitude's 2W 32-bit limbs
+// in mag; returns the sign (+1 / -1; +1 for zero).  Every thread calls it.
+__device__ int lz_load(const uint64_t* src, int W, LzShared& sh, uint32_t* mag) {
+  const int T = blockDim.x, t = threadIdx.x;
+  if (t == 0) sh.first_nz = W;
+  for (int q = t; q < W; q += T) sh.wbuf[q] = src[q];
+  __syncthreads();
+  const bool neg = (sh.wbuf[W - 1] >> 63) != 0;
+  if (neg) {
+    for (int q = t; q < W; q += T)
+      if (sh.wbuf[q]) atomicMin(&sh.first_nz, q);
+  }
+  __syncthreads();
+  const int f = sh.first_nz;
+  for (int q = t; q < W; q += T) {
+    uint64_t v = sh.wbuf[q];
+    if (neg) v = q < f ? 0ull : (q == f ? 0ull - v : ~v);
+    mag[2 * q] = (uint32_t)v;
+    mag[2 * q + 1] = (uint32_t)(v >> 32);
+  }
+  __syncthreads();
+  return neg ? -1 : 1;
+}
+
+// Adds sgn * a * b (magnitudes of na, nb limbs) to the per-thread column
+// sums lo / hi of columns k = t + T c: lo collects the low halves of the
+// limb products a_i b_(k-i), hi their high halves (which belong to column
+// k + 1).
+__device__ __forceinline__ void lz_product(const uint32_t* a, int na, const uint32_t* b, int nb,
+                                           int sgn, int64_t* lo, int64_t* hi) {
+  const int T = blockDim.x, t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < kLzCols; ++c) {
+    const int k = t + T * c;
+    const int i0 = k - nb + 1 > 0 ? k - nb + 1 : 0;
+    const int i1 = k < na - 1 ? k : na - 1;
+    uint64_t sl = 0, sh = 0;
+    for (int i = i0; i <= i1; ++i) {
+      const uint64_t p = (uint64_t)a[i] * (uint64_t)b[k - i];
+      sl += (uint32_t)p;
+      sh += p >> 32;
+    }
+    lo[c] += sgn * (int64_t)sl;
+    hi[c] += sgn * (int64_t)sh;
+  }
+}
+
+// coef[k] = lo_k + hi_(k-1) for k < NC (the per-thread sums written out).
+__device__ void lz_store_cols(const int64_t* lo, const int64_t* hi, int NC, LzShared& sh) {
+  const int T = blockDim.x, t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < kLzCols; ++c) {
+    const int k = t + T * c;
+    if (k < NC) sh.coef[k] = lo[c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kLzCols; ++c) {
+    const int k = t + T * c;
+    if (k + 1 < NC) sh.coef[k + 1] += hi[c];
+  }
+  __syncthreads();
+}
+
+// coef += sgn * |m| 2^shift (m: n limbs), split at the 32-bit column
+// boundaries (two passes, so that no two threads add to one column at once).
+__device__ void lz_add_shifted(const uint32_t* m, int n, int sgn, int shift, int NC,
+                               LzShared& sh) {
+  const int T = blockDim.x, t = threadIdx.x;
+  const int q = shift >> 5, r = shift & 31;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int l = t; l < n; l += T) {
+      const uint64_t v = (uint64_t)m[l] << r;
+      const int k = q + l + pass;
+      const int64_t part = pass == 0 ? (int64_t)(v & 0xffffffffull) : (int64_t)(v >> 32);
+      if (k < NC) sh.coef[k] += sgn * part;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void lz_zero(int64_t* lo, int64_t* hi) {
+#pragma unroll
+  for (int c = 0; c < kLzCols; ++c) lo[c] = hi[c] = 0;
+}
+
+// ------------------------------------------------------------------ kernels
+// One work-group per entry i:
+//   out_i = rne(ew w_i 2^P + sum_t sg_t a_t u_t,i), clamped to [-1, 1] if asked
+// (a_t scalars, u_t vectors; terms with a null pointer are left out).
+struct LzCombine {
+  const uint64_t* w;
+  int ew;
+  const uint64_t* a[2];
+  const uint64_t* u[2];
+  int sg[2];
+  uint64_t* out;
+  int clamp;
+};
+
+__device__ void lz_clamp_store(LzShared& sh, int P, int W, uint64_t* dst) {
+  // floor(v / 2^P) from bits [P, P + 64) (and all higher words equal to its
+  // sign extension); v > 2^P or v < -2^P become +-2^P
+  const int T = blockDim.x, t = threadIdx.x;
+  const int pq = P >> 6, pr = P & 63;
+  const uint64_t lo = sh.out[pq] >> pr;
+  const uint64_t hi = (pr && pq + 1 < W) ? sh.out[pq + 1] << (64 - pr) : 0ull;
+  const int64_t q = (int64_t)(lo | hi);
+  const uint64_t ext = q < 0 ? ~0ull : 0ull;
+  bool wide = false;
+  for (int m = pq + 2; m < W; ++m)
+    if (sh.out[m] != ext) wide = true;
+  if (pr == 0 && pq + 1 < W && sh.out[pq + 1] != ext) wide = true;
+  if (pr && pq + 1 < W && ((int64_t)sh.out[pq + 1] >> pr) != (int64_t)ext) wide = true;
+  bool rem = false;
+  for (int m = 0; m <= pq && m < W; ++m) {
+    const uint64_t v = m < pq ? sh.out[m] : (pr ? sh.out[m] & ((1ull << pr) - 1) : 0ull);
+    if (v) rem = true;
+  }
+  int cl = 0;
+  if (wide) cl = q < 0 ? -1 : 1;
+  else if (q >= 2 || (q == 1 && rem)) cl = 1;
+  else if (q <= -2) cl = -1;
+  for (int m = t; m < W; m += T) {
+    uint64_t v = sh.out[m];
+    if (cl > 0) v = m == pq ? (1ull << pr) : 0ull;
+    if (cl < 0) v = m < pq ? 0ull : (m == pq ? (~0ull << pr) : ~0ull);
+    dst[m] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kLzThreads) k_lz_combine(LzCombine cmb, int n, int P, int W,
+                                                           const int* stop) {
+  __shared__ LzShared sh;
+  const int i = blockIdx.x;
+  if (i >= n || *stop) return;
+  const int NL = 2 * W, NC = 2 * NL + 2;
+  int64_t lo[kLzCols], hi[kLzCols];
+  lz_zero(lo, hi);
+  for (int tm = 0; tm < 2; ++tm) {
+    if (!cmb.a[tm]) continue;
+    const int sa = lz_load(cmb.a[tm], W, sh, sh.mag[0]);
+    const int su = lz_load(cmb.u[tm] + (int64_t)i * W, W, sh, sh.mag[1]);
+    lz_product(sh.mag[0], NL, sh.mag[1], NL, cmb.sg[tm] * sa * su, lo, hi);
+    __syncthreads();
+  }
+  lz_store_cols(lo, hi, NC, sh);
+  if (cmb.ew) {
+    const int sw = lz_load(cmb.w + (int64_t)i * W, W, sh, sh.mag[2]);
+    lz_add_shifted(sh.mag[2], NL, sw, P, NC, sh);
+  }
+  uint64_t* dst = cmb.out + (int64_t)i * W;
+  carry_round_pack_fit(sh.coef, NC, 32, P, W, sh.cs, cmb.clamp ? sh.out : dst, sh.red);
+  if (cmb.clamp) lz_clamp_store(sh, P, W, dst);
+}
+
+// Dot product, first stage: work-group g sums sgn |u_i| |v_i| over its
+// entries [g per, (g + 1) per) into column sums part[g][k].
+__global__ void __launch_bounds__(kLzThreads) k_lz_dot_part(const uint64_t* u, const uint64_t* v,
+                                                            int n, int W, int per, int64_t* part,
+                                                            const int* stop) {
+  __shared__ LzShared sh;
+  const int g = blockIdx.x;
+  if (*stop) return;
+  const int NL = 2 * W, NC = 2 * NL + 2;
+  int64_t lo[kLzCols], hi[kLzCols];
+  lz_zero(lo, hi);
+  const int i0 = g * per, i1 = min(n, i0 + per);
+  for (int i = i0; i < i1; ++i) {
+    const int su = lz_load(u + (int64_t)i * W, W, sh, sh.mag[0]);
+    const int sv = lz_load(v + (int64_t)i * W, W, sh, sh.mag[1]);
+    lz_product(sh.mag[0], NL, sh.mag[1], NL, su * sv, lo, hi);
+    __syncthreads();
+  }
+  lz_store_cols(lo, hi, NC, sh);
+  for (int k = threadIdx.x; k < NC; k += blockDim.x) part[(int64_t)g * NC + k] = sh.coef[k];
+}
+
+// Second stage (one work-group): the column sums of all parts, rounded:
+// out = rne(sum_i u_i v_i).  count (if not null) counts the steps.
+__global__ void __launch_bounds__(kLzThreads) k_lz_dot_final(const int64_t* part, int G, int P,
+                                                             int W, uint64_t* out,
+                                                             const int* stop, int* count) {
+  __shared__ LzShared sh;
+  if (*stop) return;
+  const int NC = 4 * W + 2;
+  for (int k = threadIdx.x; k < NC; k += blockDim.x) {
+    int64_t s = 0;
+    for (int g = 0; g < G; ++g) s += part[(int64_t)g * NC + k];
+    sh.coef[k] = s;
+  }
+  __syncthreads();
+  carry_round_pack_fit(sh.coef, NC, 32, P, W, sh.cs, out, sh.red);
+  if (count && threadIdx.x == 0) *count += 1;
+}
+
+// The scalars of a step (one work-group): from nu, rho and beta, or the stop.
+// Products of two numbers already in LDS, rounded at `round` bits, with an
+// optional shifted third term; result in sh.out (W words), then reloaded.
+__device__ void lz_scalar_op(LzShared& sh, int W, int nx, int ny, int sgn, int addm, int addsgn,
+                             int addshift, int round) {
+  const int NL = 2 * W, NC = 2 * NL + 2;
+  int64_t lo[kLzCols], hi[kLzCols];
+  lz_zero(lo, hi);
+  if (nx >= 0) lz_product(sh.mag[nx], NL, sh.mag[ny], NL, sgn, lo, hi);
+  __syncthreads();
+  lz_store_cols(lo, hi, NC, sh);
+  if (addm >= 0) lz_add_shifted(sh.mag[addm], NL, addsgn, addshift, NC, sh);
+  carry_round_pack_fit(sh.coef, NC, 32, round, W, sh.cs, sh.out, sh.red);
+}
+
+__global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, int P, int W,
+                                                           int newton, uint64_t* rho,
+                                                           uint64_t* beta, int* stop) {
+  __shared__ LzShared sh;
+  __shared__ int top;
+  if (*stop) return;
+  const int T = blockDim.x, t = threadIdx.x;
+  // mag[0] = N (nu's integer; nu >= 0)
+  lz_load(nu, W, sh, sh.mag[0]);
+  if (t == 0) top = -1;
+  __syncthreads();
+  for (int l = t; l < 2 * W; l += T)
+    if (sh.mag[0][l]) atomicMax(&top, l);
+  __syncthreads();
+  const int64_t bits = top < 0 ? 0 : 32 * (int64_t)top + (32 - __clz((int)sh.mag[0][top]));
+  // stop when nu < 2^-120, i.e. N < 2^(P - 120)
+  if (top < 0 || bits - 1 < (int64_t)P - 120) {
+    for (int m = t; m < W; m += T) beta[m] = 0ull;
+    __syncthreads();
+    if (t == 0) *stop = 1;
+    return;
+  }
+  const int b = (int)(bits - P);                 // 2^(b-1) <= nu < 2^b
+  const int s = b >= 0 ? (b + 1) / 2 : -((-b) / 2);   // ceil(b / 2)
+  // mag[1] = M: mu = nu 4^-s, rounded when s > 0
+  if (s > 0) lz_scalar_op(sh, W, -1, -1, 1, 0, 1, 0, 2 * s);
+  else lz_scalar_op(sh, W, -1, -1, 1, 0, 1, -2 * s, 0);
+  lz_load(sh.out, W, sh, sh.mag[1]);
+  // mag[2] = y = 3/2
+  for (int l = t; l < 2 * W; l += T) sh.mag[2][l] = 0u;
+  __syncthreads();
+  if (t == 0) {
+    const int p = P - 1;                         // 3 * 2^(P-1): bits p and p + 1
+    sh.mag[2][p >> 5] |= 1u << (p & 31);
+    sh.mag[2][(p + 1) >> 5] |= 1u << ((p + 1) & 31);
+  }
+  __syncthreads();
+  for (int it = 0; it < newton; ++it) {
+    // t1 = rne(y y)          -> mag[3]
+    lz_scalar_op(sh, W, 2, 2, 1, -1, 1, 0, P);
+    lz_load(sh.out, W, sh, sh.mag[3]);
+    // t2 = rne(M t1)         -> mag[3]
+    lz_scalar_op(sh, W, 1, 3, 1, -1, 1, 0, P);
+    const int s2 = lz_load(sh.out, W, sh, sh.mag[3]);
+    // y = rne((3 y 2^P - y t2) / 2): 3 y 2^P as y 2^(P+1) + y 2^P
+    {
+      const int NL = 2 * W, NC = 2 * NL + 2;
+      int64_t lo[kLzCols], hi[kLzCols];
+      lz_zero(lo, hi);
+      lz_product(sh.mag[2], NL, sh.mag[3], NL, -s2, lo, hi);
+      __syncthreads();
+      lz_store_cols(lo, hi, NC, sh);
+      lz_add_shifted(sh.mag[2], NL, 1, P + 1, NC, sh);
+      lz_add_shifted(sh.mag[2], NL, 1, P, NC, sh);
+      carry_round_pack_fit(sh.coef, NC, 32, P + 1, W, sh.cs, sh.out, sh.red);
+    }
+    lz_load(sh.out, W, sh, sh.mag[2]);
+  }
+  // rho = y 2^-s (mag[2] -> mag[4] and rho)
+  if (s > 0) lz_scalar_op(sh, W, -1, -1, 1, 2, 1, 0, s);
+  else lz_scalar_op(sh, W, -1, -1, 1, 2, 1, -s, 0);
+  for (int m = t; m < W; m += T) rho[m] = sh.out[m];
+  lz_load(sh.out, W, sh, sh.mag[4]);
+  // beta = rne(N rho)
+  lz_scalar_op(sh, W, 0, 4, 1, -1, 1, 0, P);
+  for (int m = t; m < W; m += T) beta[m] = sh.out[m];
+}
+
+__global__ void k_lz_init(int* stop, uint64_t* zero, int W) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    stop[0] = 0;
+    stop[1] = 0;
+  }
+  for (int m = threadIdx.x; m < W; m += blockDim.x) zero[m] = 0ull;
+}
+
+__global__ void k_lz_count(const int* stop, int32_t* steps_done) {
+  if (threadIdx.x == 0) *steps_done = stop[1];
+}
+
+__global__ void k_lz_copy(const uint64_t* src, uint64_t* dst, int64_t words, const int* stop) {
+  if (*stop) return;
+  for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < words;
+       m += (int64_t)gridDim.x * blockDim.x)
+    dst[m] = src[m];
+}
+
+struct LzLayout {
+  int W, G, per, NC;
+  int64_t off_stop, off_zero, off_nu, off_rho, off_vec[3], off_part, off_mv, bytes;
+};
+
+LzLayout lz_layout(const hmv_plan* p) {
+  LzLayout L{};
+  const int64_t n = p->n;
+  L.W = (int)words_of(p->P);
+  L.NC = 4 * L.W + 2;
+  L.G = (int)(n < 256 ? n : 256);
+  L.per = (int)((n + L.G - 1) / L.G);
+  int64_t o = kStatusBytes;
+  L.off_stop = o;
+  o += kStopBytes;
+  L.off_zero = o;
+  o += align_up(8 * (int64_t)L.W);
+  L.off_nu = o;
+  o += align_up(8 * (int64_t)L.W);
+  L.off_rho = o;
+  o += align_up(8 * (int64_t)L.W);
+  for (int k = 0; k < 3; ++k) {
+    L.off_vec[k] = o;
+    o += align_up(8 * n * L.W);
+  }
+  L.off_part = o;
+  o += align_up(8 * (int64_t)L.G * L.NC);
+  L.off_mv = o;
+  o += kStatusBytes + p->mv_scratch;
+  L.bytes = o;
+  return L;
+}
+
+}  // namespace
+}  // namespace hmv
+
+extern "C" {
+
+int64_t hmv_lanczos_workspace_bytes(const hmv_plan* p) {
+  if (!p) return HMV_EINVAL;
+  return hmv::lz_layout(p).bytes;
+}
+
+int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* alpha,
+                uint64_t* beta, int32_t* steps_done, uint64_t* basis, void* ws, int64_t ws_bytes,
+                void* stream) {
+  using namespace hmv;
+  if (!p || !q1 || !alpha || !beta || !steps_done || !ws || steps < 1) return HMV_EINVAL;
+  if (p->kind != HMV_HANKEL) return HMV_EINVAL;     // a symmetric matrix
+  const LzLayout L = lz_layout(p);
+  if (ws_bytes < L.bytes) return HMV_ENOMEM;
+  clear_stale_error();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  DevStatus* st = reinterpret_cast<DevStatus*>(base);
+  int* stop = reinterpret_cast<int*>(base + L.off_stop);
+  uint64_t* zero = reinterpret_cast<uint64_t*>(base + L.off_zero);
+  uint64_t* nu = reinterpret_cast<uint64_t*>(base + L.off_nu);
+  uint64_t* rho = reinterpret_cast<uint64_t*>(base + L.off_rho);
+  uint64_t* vec[3];
+  for (int k = 0; k < 3; ++k) vec[k] = reinterpret_cast<uint64_t*>(base + L.off_vec[k]);
+  int64_t* part = reinterpret_cast<int64_t*>(base + L.off_part);
+  char* mv = base + L.off_mv;
+  const int n = (int)p->n, W = L.W, P = p->P;
+  const int64_t nw = (int64_t)n * W;
+  hipError_t e = launch_clear_status(st, s);
+  if (e != hipSuccess) return status_from_hip(e, "lanczos: clear status");
+  hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(256), 0, s, stop, zero, W);
+  e = hipMemcpyAsync(vec[0], q1, 8 * nw, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return status_from_hip(e, "lanczos: start vector");
+  // vec[q] = q_j, vec[qp] = q_(j-1) (zero at first), vec[wv] = w, then r
+  int q = 0, qp = 1, wv = 2;
+  const int newton = 32 - __builtin_clz((unsigned)P) + 6;     // bitlen(P) + 6
+  // q_0 is never read: beta_1 = 0 leaves its term out of the first update
+  for (int j = 0; j < steps; ++j) {
+    const uint64_t* beta_j = j == 0 ? zero : beta + (int64_t)(j - 1) * W;
+    uint64_t* alpha_j = alpha + (int64_t)j * W;
+    uint64_t* beta_j1 = beta + (int64_t)j * W;
+    if (basis) {
+      hipLaunchKernelGGL(k_lz_copy, dim3(256), dim3(256), 0, s, vec[q], basis + (int64_t)j * nw,
+                         nw, stop);
+    }
+    // w = A q_j
+    int rc = plan_matvec_parts(p, vec[q], vec[wv], st, mv + kStatusBytes, p->mv_scratch, s,
+                               nullptr, false);
+    if (rc != HMV_OK) return rc;
+    // alpha_j = rne(q . w)
+    hipLaunchKernelGGL(k_lz_dot_part, dim3(L.G), dim3(kLzThreads), 0, s, vec[q], vec[wv], n, W,
+                       L.per, part, stop);
+    hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, part, L.G, P, W,
+                       alpha_j, stop, stop + 1);
+    // r = rne(w - alpha q_j - beta_j q_j-1), in place of w
+    LzCombine c{};
+    c.w = vec[wv];
+    c.ew = 1;
+    c.a[0] = alpha_j;
+    c.u[0] = vec[q];
+    c.sg[0] = -1;
+    c.a[1] = j == 0 ? nullptr : beta_j;
+    c.u[1] = vec[qp];
+    c.sg[1] = -1;
+    c.out = vec[wv];
+    c.clamp = 0;
+    hipLaunchKernelGGL(k_lz_combine, dim3(n), dim3(kLzThreads), 0, s, c, n, P, W, stop);
+    // nu = rne(r . r); rho, beta_j+1 (or the stop)
+    hipLaunchKernelGGL(k_lz_dot_part, dim3(L.G), dim3(kLzThreads), 0, s, vec[wv], vec[wv], n, W,
+                       L.per, part, stop);
+    hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, part, L.G, P, W, nu,
+                       stop, nullptr);
+    hipLaunchKernelGGL(k_lz_scalars, dim3(1), dim3(kLzThreads), 0, s, nu, P, W, newton, rho,
+                       beta_j1, stop);
+    // q_j+1 = clamp(rne(rho r)), in place of q_j-1
+    LzCombine d{};
+    d.w = nullptr;
+    d.ew = 0;
+    d.a[0] = rho;
+    d.u[0] = vec[wv];
+    d.sg[0] = 1;
+    d.out = vec[qp];
+    d.clamp = 1;
+    hipLaunchKernelGGL(k_lz_combine, dim3(n), dim3(kLzThreads), 0, s, d, n, P, W, stop);
+    e = hipGetLastError();
+    if (e != hipSuccess) return status_from_hip(e, "lanczos step");
+    const int nq = qp;
+    qp = q;
+    q = nq;
+  }
+  hipLaunchKernelGGL(k_lz_count, dim3(1), dim3(64), 0, s, stop, steps_done);
+  return status_from_hip(hipGetLastError(), "lanczos: step count");
+}
+
+}  // extern "C"

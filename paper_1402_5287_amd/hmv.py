@@ -41,6 +41,8 @@ SIGNATURES = {
                             _vp, _c_i64, _vp]),
     "hmv_plan_matvec": (_c_int, [_vp, _vp, _vp, _vp, _c_i64, _vp]),
     "hmv_plan_matvec_noalloc": (_c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "hmv_lanczos_workspace_bytes": (_c_i64, [_vp]),
+    "hmv_lanczos": (_c_int, [_vp, _vp, _c_i32, _vp, _vp, _vp, _vp, _vp, _c_i64, _vp]),
     "hmv_fplan_bytes": (_c_i64, [_c_int, _c_i64, _c_i32, _c_i32]),
     "hmv_fplan_workspace_bytes": (_c_i64, [_c_int, _c_i64, _c_i32, _c_i32]),
     "hmv_fplan_h": (_c_int, [ctypes.POINTER(_vp), _c_int, _vp, _vp, _c_i64, _c_i32, _c_i32, _vp,
@@ -241,6 +243,25 @@ class Plan:
         if check:
             _check(rc, "plan_matvec")
         return rc
+
+    def lanczos(self, q1, steps: int, basis: bool = False, stream=None):
+        """Lanczos tridiagonalisation from q1 (device words): returns device
+        tensors (alpha, beta, steps_done, basis or None, ws); see hmv_lanczos."""
+        import torch
+        W = words(self.P)
+        dev = self.mem.device
+        alpha = torch.zeros((steps, W), dtype=torch.int64, device=dev)
+        beta = torch.zeros((steps, W), dtype=torch.int64, device=dev)
+        done = torch.zeros(1, dtype=torch.int32, device=dev)
+        bas = torch.zeros((steps, self.n, W), dtype=torch.int64, device=dev) if basis else None
+        nb = lib().hmv_lanczos_workspace_bytes(self.handle)
+        if nb < 0:
+            raise HmvError(int(nb), "hmv_lanczos_workspace_bytes")
+        ws = workspace(int(nb), device=dev)
+        _check(lib().hmv_lanczos(self.handle, _ptr(q1), int(steps), _ptr(alpha), _ptr(beta),
+                                 _ptr(done), _ptr(bas), _ptr(ws), ws.numel(), _stream(stream)),
+               "lanczos")
+        return alpha, beta, done, bas, ws
 
     def multi_workspace(self, k: int):
         b = lib().hmv_plan_multi_workspace_bytes(self.handle, int(k))
