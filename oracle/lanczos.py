@@ -21,11 +21,14 @@ defined on integers (value X * 2**-P) so that the GPU result is unique:
 rne(.) rounds an exact value to the nearest multiple of 2**-P, ties to
 even.  rsqrt: with b = the bit length of nu's integer minus P (so that
 2**(b-1) <= nu < 2**b) and s = ceil(b / 2), mu = nu 4**-s lies in [1/4, 1)
-(exact when s <= 0, one rounding otherwise); Newton's iteration for
-1/sqrt(mu), y <- y (3 - mu y^2) / 2, starts at y = 3/2 and runs
-bitlen(P) + 6 times, each step as rne(y y), rne(mu (y y)), 3 - that, and
-rne of (y times that) / 2; finally rho = y 2**-s (exact when s <= 0,
-rounded otherwise).
+(exact when s <= 0, one rounding otherwise).  Newton's iteration for
+1/sqrt(mu), y <- y (3 - mu y^2) / 2, runs with a working precision p that
+doubles: p = min(P, 64) first, from y = 3/2, for 9 steps; then p grows to
+min(P, 2p - 8) (y shifted up exactly) with one step per level, and two
+steps at p = P.  A step at precision p rounds at 2**-p: rne(y y),
+rne(mu_p (y y)) with mu_p = mu rounded to p bits, 3 - that, and rne of
+(y times that) / 2.  Finally rho = y 2**-s (exact when s <= 0, rounded
+otherwise).
 """
 from __future__ import annotations
 
@@ -38,8 +41,19 @@ def rne(S: int, k: int) -> int:
     return fp.round_half_even(S, k) if k > 0 else S
 
 
-def newton_steps(P: int) -> int:
-    return P.bit_length() + 6
+NEWTON_START_BITS = 64      # working precision of the first Newton steps
+NEWTON_START_STEPS = 9      # steps from y = 3/2 at that precision
+NEWTON_FINAL_STEPS = 2      # steps at the full precision P
+
+
+def newton_schedule(P: int) -> list:
+    """(precision, steps) of the Newton levels for P fractional bits."""
+    p = min(P, NEWTON_START_BITS)
+    out = [(p, NEWTON_START_STEPS)]
+    while p < P:
+        p = min(P, 2 * p - 8)
+        out.append((p, NEWTON_FINAL_STEPS if p == P else 1))
+    return out
 
 
 def rsqrt(N: int, P: int) -> int:
@@ -47,12 +61,16 @@ def rsqrt(N: int, P: int) -> int:
     b = N.bit_length() - P
     s = -((-b) // 2)                              # ceil(b / 2)
     M = rne(N, 2 * s) if s > 0 else N << (-2 * s)  # mu = M 2**-P in [1/4, 1]
-    y = 3 << (P - 1)                              # 3/2
-    three = 3 << P
-    for _ in range(newton_steps(P)):
-        t1 = rne(y * y, P)
-        t2 = rne(M * t1, P)
-        y = rne(y * (three - t2), P + 1)
+    y, prev = 0, 0
+    for p, steps in newton_schedule(P):
+        y = 3 << (p - 1) if prev == 0 else y << (p - prev)
+        Mp = rne(M, P - p)                        # mu at p bits
+        three = 3 << p
+        for _ in range(steps):
+            t1 = rne(y * y, p)
+            t2 = rne(Mp * t1, p)
+            y = rne(y * (three - t2), p + 1)
+        prev = p
     return rne(y, s) if s > 0 else y << (-s)
 
 

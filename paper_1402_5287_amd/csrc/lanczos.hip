@@ -9,8 +9,10 @@
 //   r_i     = rne(w_i - alpha_j q_j,i - beta_j q_j-1,i)
 //   nu      = rne(sum_i r_i^2); stop when nu < 2^-120
 //   rho     = 1/sqrt(nu) by a fixed Newton iteration on mu = nu 4^-s in
-//             [1/4, 1):  y <- rne(rne(3 y 2^P - y rne(mu rne(y y))) / 2),
-//             y_0 = 3/2, bitlen(P) + 6 steps, then rho = y 2^-s
+//             [1/4, 1):  y <- rne((3 y 2^p - y rne(mu_p rne(y y))) / 2) at a
+//             working precision p that doubles (64 bits first, 9 steps from
+//             y = 3/2; then min(P, 2p - 8), one step per level, two at P;
+//             mu_p = mu rounded to p bits), then rho = y 2^-s
 //   beta_j+1 = rne(nu rho),   q_j+1,i = rne(r_i rho) clamped to [-1, 1]
 //
 // The exact expressions are big-integer sums of products.  A work-group
@@ -248,32 +250,43 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_dot_final(const int64_t* part
 }
 
 // The scalars of a step (one work-group): from nu, rho and beta, or the stop.
-// Products of two numbers already in LDS, rounded at `round` bits, with an
-// optional shifted third term; result in sh.out (W words), then reloaded.
-__device__ void lz_scalar_op(LzShared& sh, int W, int nx, int ny, int sgn, int addm, int addsgn,
-                             int addshift, int round) {
-  const int NL = 2 * W, NC = 2 * NL + 2;
+// A product of two numbers already in LDS (magnitudes mag[nx], mag[ny], nl
+// limbs each; nx < 0 for none) plus an optional shifted term addsgn
+// mag[addm] 2^addshift, rounded at `round` bits (0: exact); the result goes
+// to sh.out (W words).
+__device__ void lz_scalar_op(LzShared& sh, int W, int nl, int nx, int ny, int sgn, int addm,
+                             int addsgn, int addshift, int round) {
+  const int NC = 2 * nl + 2;
   int64_t lo[kLzCols], hi[kLzCols];
   lz_zero(lo, hi);
-  if (nx >= 0) lz_product(sh.mag[nx], NL, sh.mag[ny], NL, sgn, lo, hi);
+  if (nx >= 0) lz_product(sh.mag[nx], nl, sh.mag[ny], nl, sgn, lo, hi);
   __syncthreads();
   lz_store_cols(lo, hi, NC, sh);
-  if (addm >= 0) lz_add_shifted(sh.mag[addm], NL, addsgn, addshift, NC, sh);
+  if (addm >= 0) lz_add_shifted(sh.mag[addm], nl, addsgn, addshift, NC, sh);
   carry_round_pack_fit(sh.coef, NC, 32, round, W, sh.cs, sh.out, sh.red);
 }
 
+// Limbs that hold the values of a Newton step at working precision p (every
+// operand below 2^(p+4) in magnitude, with one limb to spare).
+__device__ __forceinline__ int lz_newton_limbs(int p) { return (p + 4 + 31) / 32 + 1; }
+
+// The Newton levels (working precision, steps): p = min(P, 64) for 9 steps
+// from y = 3/2, then p = min(P, 2p - 8) for one step each, two at p = P.
+constexpr int kNewtonStartBits = 64, kNewtonStartSteps = 9, kNewtonFinalSteps = 2;
+
 __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, int P, int W,
-                                                           int newton, uint64_t* rho,
-                                                           uint64_t* beta, int* stop) {
+                                                           uint64_t* rho, uint64_t* beta,
+                                                           int* stop) {
   __shared__ LzShared sh;
   __shared__ int top;
   if (*stop) return;
   const int T = blockDim.x, t = threadIdx.x;
+  const int NLF = 2 * W;                         // full-precision limbs
   // mag[0] = N (nu's integer; nu >= 0)
   lz_load(nu, W, sh, sh.mag[0]);
   if (t == 0) top = -1;
   __syncthreads();
-  for (int l = t; l < 2 * W; l += T)
+  for (int l = t; l < NLF; l += T)
     if (sh.mag[0][l]) atomicMax(&top, l);
   __syncthreads();
   const int64_t bits = top < 0 ? 0 : 32 * (int64_t)top + (32 - __clz((int)sh.mag[0][top]));
@@ -286,47 +299,63 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
   }
   const int b = (int)(bits - P);                 // 2^(b-1) <= nu < 2^b
   const int s = b >= 0 ? (b + 1) / 2 : -((-b) / 2);   // ceil(b / 2)
-  // mag[1] = M: mu = nu 4^-s, rounded when s > 0
-  if (s > 0) lz_scalar_op(sh, W, -1, -1, 1, 0, 1, 0, 2 * s);
-  else lz_scalar_op(sh, W, -1, -1, 1, 0, 1, -2 * s, 0);
+  // mag[1] = M: mu = nu 4^-s at P bits, rounded when s > 0
+  if (s > 0) lz_scalar_op(sh, W, NLF, -1, -1, 1, 0, 1, 0, 2 * s);
+  else lz_scalar_op(sh, W, NLF, -1, -1, 1, 0, 1, -2 * s, 0);
   lz_load(sh.out, W, sh, sh.mag[1]);
-  // mag[2] = y = 3/2
-  for (int l = t; l < 2 * W; l += T) sh.mag[2][l] = 0u;
-  __syncthreads();
-  if (t == 0) {
-    const int p = P - 1;                         // 3 * 2^(P-1): bits p and p + 1
-    sh.mag[2][p >> 5] |= 1u << (p & 31);
-    sh.mag[2][(p + 1) >> 5] |= 1u << ((p + 1) & 31);
-  }
-  __syncthreads();
-  for (int it = 0; it < newton; ++it) {
-    // t1 = rne(y y)          -> mag[3]
-    lz_scalar_op(sh, W, 2, 2, 1, -1, 1, 0, P);
-    lz_load(sh.out, W, sh, sh.mag[3]);
-    // t2 = rne(M t1)         -> mag[3]
-    lz_scalar_op(sh, W, 1, 3, 1, -1, 1, 0, P);
-    const int s2 = lz_load(sh.out, W, sh, sh.mag[3]);
-    // y = rne((3 y 2^P - y t2) / 2): 3 y 2^P as y 2^(P+1) + y 2^P
-    {
-      const int NL = 2 * W, NC = 2 * NL + 2;
-      int64_t lo[kLzCols], hi[kLzCols];
-      lz_zero(lo, hi);
-      lz_product(sh.mag[2], NL, sh.mag[3], NL, -s2, lo, hi);
+  int p = P < kNewtonStartBits ? P : kNewtonStartBits, prev = 0;
+  for (;;) {
+    const int nl = lz_newton_limbs(p);
+    const int steps = prev == 0 ? kNewtonStartSteps : (p == P ? kNewtonFinalSteps : 1);
+    // mag[2] = y: 3/2 at the first level, else y shifted up by p - prev bits
+    if (prev == 0) {
+      for (int l = t; l < NLF; l += T) sh.mag[2][l] = 0u;
       __syncthreads();
-      lz_store_cols(lo, hi, NC, sh);
-      lz_add_shifted(sh.mag[2], NL, 1, P + 1, NC, sh);
-      lz_add_shifted(sh.mag[2], NL, 1, P, NC, sh);
-      carry_round_pack_fit(sh.coef, NC, 32, P + 1, W, sh.cs, sh.out, sh.red);
+      if (t == 0) {                              // 3 * 2^(p-1): bits p - 1 and p
+        sh.mag[2][(p - 1) >> 5] |= 1u << ((p - 1) & 31);
+        sh.mag[2][p >> 5] |= 1u << (p & 31);
+      }
+      __syncthreads();
+    } else {
+      lz_scalar_op(sh, W, nl, -1, -1, 1, 2, 1, p - prev, 0);
+      lz_load(sh.out, W, sh, sh.mag[2]);
     }
-    lz_load(sh.out, W, sh, sh.mag[2]);
+    // mag[4] = mu_p: M rounded to p bits
+    if (p < P) lz_scalar_op(sh, W, NLF, -1, -1, 1, 1, 1, 0, P - p);
+    else lz_scalar_op(sh, W, NLF, -1, -1, 1, 1, 1, 0, 0);
+    lz_load(sh.out, W, sh, sh.mag[4]);
+    for (int it = 0; it < steps; ++it) {
+      // t1 = rne(y y)          -> mag[3]
+      lz_scalar_op(sh, W, nl, 2, 2, 1, -1, 1, 0, p);
+      lz_load(sh.out, W, sh, sh.mag[3]);
+      // t2 = rne(mu_p t1)      -> mag[3]
+      lz_scalar_op(sh, W, nl, 4, 3, 1, -1, 1, 0, p);
+      const int s2 = lz_load(sh.out, W, sh, sh.mag[3]);
+      // y = rne((3 y 2^p - y t2) / 2): 3 y 2^p as y 2^(p+1) + y 2^p
+      {
+        const int NC = 2 * nl + 2;
+        int64_t lo[kLzCols], hi[kLzCols];
+        lz_zero(lo, hi);
+        lz_product(sh.mag[2], nl, sh.mag[3], nl, -s2, lo, hi);
+        __syncthreads();
+        lz_store_cols(lo, hi, NC, sh);
+        lz_add_shifted(sh.mag[2], nl, 1, p + 1, NC, sh);
+        lz_add_shifted(sh.mag[2], nl, 1, p, NC, sh);
+        carry_round_pack_fit(sh.coef, NC, 32, p + 1, W, sh.cs, sh.out, sh.red);
+      }
+      lz_load(sh.out, W, sh, sh.mag[2]);
+    }
+    if (p == P) break;
+    prev = p;
+    p = 2 * p - 8 < P ? 2 * p - 8 : P;
   }
   // rho = y 2^-s (mag[2] -> mag[4] and rho)
-  if (s > 0) lz_scalar_op(sh, W, -1, -1, 1, 2, 1, 0, s);
-  else lz_scalar_op(sh, W, -1, -1, 1, 2, 1, -s, 0);
+  if (s > 0) lz_scalar_op(sh, W, NLF, -1, -1, 1, 2, 1, 0, s);
+  else lz_scalar_op(sh, W, NLF, -1, -1, 1, 2, 1, -s, 0);
   for (int m = t; m < W; m += T) rho[m] = sh.out[m];
   lz_load(sh.out, W, sh, sh.mag[4]);
   // beta = rne(N rho)
-  lz_scalar_op(sh, W, 0, 4, 1, -1, 1, 0, P);
+  lz_scalar_op(sh, W, NLF, 0, 4, 1, -1, 1, 0, P);
   for (int m = t; m < W; m += T) beta[m] = sh.out[m];
 }
 
@@ -421,7 +450,6 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
   if (e != hipSuccess) return status_from_hip(e, "lanczos: start vector");
   // vec[q] = q_j, vec[qp] = q_(j-1) (zero at first), vec[wv] = w, then r
   int q = 0, qp = 1, wv = 2;
-  const int newton = 32 - __builtin_clz((unsigned)P) + 6;     // bitlen(P) + 6
   // q_0 is never read: beta_1 = 0 leaves its term out of the first update
   for (int j = 0; j < steps; ++j) {
     const uint64_t* beta_j = j == 0 ? zero : beta + (int64_t)(j - 1) * W;
@@ -458,7 +486,7 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
                        L.per, part, stop);
     hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, part, L.G, P, W, nu,
                        stop, nullptr);
-    hipLaunchKernelGGL(k_lz_scalars, dim3(1), dim3(kLzThreads), 0, s, nu, P, W, newton, rho,
+    hipLaunchKernelGGL(k_lz_scalars, dim3(1), dim3(kLzThreads), 0, s, nu, P, W, rho,
                        beta_j1, stop);
     // q_j+1 = clamp(rne(rho r)), in place of q_j-1
     LzCombine d{};
