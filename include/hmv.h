@@ -122,6 +122,8 @@ typedef struct {
                              column (the error bound allows it), else Nz/2 + 1;
                              0 for the other paths                             */
   int32_t reserved;
+  int32_t x_tile, y_tile; /* split-FFT: bins per tile of the stored spectra of x
+                             and of y (2, 4 or 8; picked by the tuning runs) */
 } hmv_plan_info_t;
 
 int64_t hmv_plan_bytes(int kind, int64_t n, int32_t P, int algo);
@@ -157,13 +159,16 @@ int64_t hmv_plan_multi_workspace_bytes(const hmv_plan* plan, int32_t k);
 int hmv_plan_matvec_multi(const hmv_plan* plan, int32_t k, const uint64_t* x, uint64_t* y,
                           void* ws, int64_t ws_bytes, void* stream, void* const* events);
 /* Launch tuning of the split-FFT path (on by default).  When on, planning a
- * shape (n, P, limb width) for the first time in the process also times
- * each launch variant of the index-axis pass (radix-16 or radix-8 register
- * transforms; XCD-grouped or linear column order) and of the inverse limb
- * pass (radix 16 or 8) on the plan's own data, and keeps the fastest; later
- * plans of that shape, and one-shot calls, reuse the choice.  Every variant
- * computes the same words.  Off: the first variant of each.  Process-wide;
- * returns HMV_EINVAL for values other than 0 and 1.                        */
+ * shape (n, P, limb width) for the first time in the process also times, on
+ * the plan's own data (the first n rows of h standing in for x), every pair
+ * of tile widths (2, 4 or 8 bins) of the stored spectra of x and of y over
+ * a whole matvec, then at the chosen widths each launch variant of the
+ * index-axis pass (radix-16 or radix-8 register transforms; XCD-grouped or
+ * linear column order) and of the inverse limb pass (radix 16 or 8), and
+ * keeps the fastest; later plans of that shape, and one-shot calls, reuse
+ * the choice.  Every choice computes the same words.  Off: the first
+ * variant of each and tiles of 4 bins.  Process-wide; returns HMV_EINVAL
+ * for values other than 0 and 1.                                           */
 int hmv_autotune(int32_t on);
 int hmv_plan_info(const hmv_plan* plan, hmv_plan_info_t* info);
 int hmv_plan_destroy(hmv_plan* plan);
@@ -279,7 +284,6 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
                      void* stream);
 /* Number of kernel launches hmv_batch_matvec makes for these problems. */
 int32_t hmv_batch_launches(const hmv_problem* probs, int32_t count);
-
 /* ---------------------------------------------------------------- serving
  * A request scheduler for sessions of planned matvecs (continuous
  * batching).  The caller provides one device pool (pool_bytes) from which
@@ -339,6 +343,10 @@ int hmv_debug_force_variants(int32_t cols_variant, int32_t rows_inv_variant);
  * packed where the error bound allows it).  The bound is still enforced.
  * Returns HMV_EINVAL for values outside -1..1.                             */
 int hmv_debug_force_layout(int32_t z3, int32_t pack);
+/* tests only: spectrum tile widths (2, 4 or 8 bins) of later split-FFT
+ * plans for the spectra of x and of y; -1 keeps the tuned choice.
+ * Returns HMV_EINVAL for other values.                                     */
+int hmv_debug_force_tiles(int32_t x_tile, int32_t y_tile);
 /* tests only: spin limit of the dependency waits of the single-launch batch
  * driver (switched off in this build; kept for its test); 0 = default.     */
 int hmv_debug_batch_spin_limit(int32_t spins);

@@ -17,10 +17,11 @@
 //
 // Spectra between passes live in HBM in column tiles of TW complex values:
 // element (row, k) of a [rows][C] half-plane sits at ((k/TW) rows + row) TW +
-// k%TW (TW = 4 for the spectra of x and of y: a row pass writes or reads 64
-// contiguous bytes of a row per tile, a column pass reads one 16-byte slot of
-// them while the TW - 1 neighbouring columns of the tile run on the same XCD,
-// column order being remapped per XCD, and hit in its L2).
+// k%TW (a row pass writes or reads 16 TW contiguous bytes of a row per tile, a
+// column pass reads one 16-byte slot of them while the TW - 1 neighbouring
+// columns of the tile run on the same XCD, column order being remapped per
+// XCD, and hit in its L2).  TW = 2^lt is a run-time choice per plan, picked
+// for the spectra of x and of y separately by the planner's timing runs.
 #include <mutex>
 #include <vector>
 
@@ -87,20 +88,11 @@ __device__ __forceinline__ int xcd_slot(int b, int grid) {
   return (b & 7) * q + (b >> 3);
 }
 
-// Spectra of rows are stored in tiles of TW bins: bin k of row `row` at
-// ((k / TW) rows + row) TW + k % TW.  The row passes touch TW contiguous
+// Spectra of rows are stored in tiles of TW = 2^lt bins: bin k of row `row`
+// at ((k / TW) rows + row) TW + k % TW.  The row passes touch TW contiguous
 // bins per row, the index-axis pass reads a bin column at stride TW.
-#ifndef HMV_X1_TILE
-#define HMV_X1_TILE 4
-#endif
-#ifndef HMV_Y1_TILE
-#define HMV_Y1_TILE 4
-#endif
-constexpr int kX1Tile = HMV_X1_TILE;   // spectra of x (and of h while planning)
-constexpr int kY1Tile = HMV_Y1_TILE;   // spectra of y
-template <int TW>
-__device__ __forceinline__ int64_t tidx(int k, int row, int rows) {
-  return ((int64_t)(k / TW) * rows + row) * TW + (k % TW);
+__device__ __forceinline__ int64_t tidx(int k, int row, int rows, int lt) {
+  return ((((int64_t)(k >> lt)) * rows + row) << lt) + (k & ((1 << lt) - 1));
 }
 __device__ __forceinline__ int64_t tile_index(int k, int row, int rows) {
   return ((int64_t)(k >> 3) * rows + row) * 8 + (k & 7);
@@ -160,12 +152,12 @@ __global__ void __launch_bounds__(256) k_h_norms(const uint64_t* __restrict__ h,
 //   X[k] = 1/2 (Z[k] + conj Z[M-k]) - i/2 w^k (Z[k] - conj Z[M-k]),
 // stored to row r of the tiled spectrum.  A thread's root loads are issued
 // eight at a time so that they are in flight together.
-// Stored in tiles of TW bins (tidx).
+// Stored in tiles of 2^lt bins (tidx).
 // PACK0: bins 0 and M, both real, share column 0 as X[0] + i X[M] (columns
 // 0 .. M-1 are written); otherwise bins 0 .. M go to columns 0 .. M.
-template <int TW, bool PACK0 = false>
+template <bool PACK0 = false>
 __device__ inline void pack_real_row(const double2* buf, int M, double2* __restrict__ out, int r,
-                                     int rows_alloc) {
+                                     int rows_alloc, int lt) {
   const int T = blockDim.x, t = threadIdx.x;
   const int rs = kRealTwN / (2 * M);
   for (int k0 = t; k0 <= M; k0 += 8 * T) {
@@ -182,7 +174,7 @@ __device__ inline void pack_real_row(const double2* buf, int M, double2* __restr
         const double2 zk = buf[lds_slot(k & (M - 1))], zm = buf[lds_slot((M - k) & (M - 1))];
         const double2 A = cadd(zk, conj2(zm)), B = csub(zk, conj2(zm));
         const double2 Q = cmul(wv[u], B);
-        const int64_t o = tidx<TW>(k, r, rows_alloc);
+        const int64_t o = tidx(k, r, rows_alloc, lt);
         if constexpr (PACK0) {
           // X[0] = Z[0].re + Z[0].im, X[M] = Z[0].re - Z[0].im
           if (k == 0) out[o] = make_double2(zk.x + zk.y, zk.x - zk.y);
@@ -201,7 +193,7 @@ template <int LOGM>
 __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict__ in, int W, int P,
                                                      int w, int L, int count, int gather_n,
                                                      double2* __restrict__ out, int rows_alloc,
-                                                     int pack, DevStatus* st) {
+                                                     int pack, int lt, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint64_t wd[kMaxWords];
   __shared__ uint32_t red[32];
@@ -228,8 +220,8 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds_t<LOGM>(buf, -1);
-  if (pack) pack_real_row<kX1Tile, true>(buf, M, out, r, rows_alloc);
-  else pack_real_row<kX1Tile, false>(buf, M, out, r, rows_alloc);
+  if (pack) pack_real_row<true>(buf, M, out, r, rows_alloc, lt);
+  else pack_real_row<false>(buf, M, out, r, rows_alloc, lt);
 }
 
 // The index-axis transforms of N_t = 2 Nh points are split by one radix-2
@@ -264,7 +256,7 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
 // (above).
 template <int LOGNH>
 __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H1, int rows,
-                                                   int C, double scale, int pack,
+                                                   int C, double scale, int pack, int lt,
                                                    double2* __restrict__ Hh) {
   extern __shared__ double2 buf[];
   const int c = xcd_slot(blockIdx.x, gridDim.x);
@@ -274,7 +266,7 @@ __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H
   constexpr int rs = kRealTwN >> logNt;
   const int t = threadIdx.x;
   const bool act = t < Ta;
-  const double2* col = H1 + tidx<kX1Tile>(c, 0, rows);   // bin column, stride kX1Tile
+  const double2* col = H1 + tidx(c, 0, rows, lt);       // bin column, stride 2^lt
   double2* he = Hh + (int64_t)c * (2 * Nh);
   double2* ho = he + Nh;
   double2 v[16];
@@ -285,8 +277,8 @@ __global__ void __launch_bounds__(512) k_cols_plan(const double2* __restrict__ H
 #pragma unroll
       for (int j = 0; j < per; ++j) {
         const int s = t + Ta * j;
-        const double2 lo = col[(int64_t)(s < rows ? s : 0) * kX1Tile];
-        const double2 hi = col[(int64_t)(s + Nh < rows ? s + Nh : 0) * kX1Tile];
+        const double2 lo = col[(int64_t)(s < rows ? s : 0) << lt];
+        const double2 hi = col[(int64_t)(s + Nh < rows ? s + Nh : 0) << lt];
         const double2 l = s < rows ? lo : make_double2(0.0, 0.0);
         const double2 u = s + Nh < rows ? hi : make_double2(0.0, 0.0);
         v[j] = half == 0 ? cadd(l, u) : cmul(csub(l, u), real_root(s, rs));
@@ -369,7 +361,7 @@ __device__ __forceinline__ void packed_product(double2* v, double2* buf, const d
 template <int LOGNH, int R>
 __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
     const double2* __restrict__ X1, const double2* __restrict__ Hh, int n, int C, int linear,
-    int pack, int kvec, double2* __restrict__ Y1) {
+    int pack, int kvec, int ltx, int lty, double2* __restrict__ Y1) {
   extern __shared__ double2 buf[];
   // block b: vector (b / 8) mod kvec, column slot 8 ((b / 8) / kvec) + b mod 8
   const int bq = (int)blockIdx.x >> 3;
@@ -383,11 +375,12 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
   const int t = threadIdx.x;
   const bool act = t < Ta;
   const int rows = kvec * n;
-  // bin column of x, stride kX1Tile
-  const double2* xcol = X1 + tidx<kX1Tile>(c, vec * n, rows);
+  const bool packed = pack && c == 0;                // uniform
+  // bin column of x, stride 2^ltx
+  const double2* xcol = X1 + tidx(c, vec * n, rows, ltx);
   const double2* he = Hh + (int64_t)c * (2 * Nh);
   const double2* ho = he + Nh;
-  double2* ycol = Y1 + tidx<kY1Tile>(c, vec * n, rows);
+  double2* ycol = Y1 + tidx(c, vec * n, rows, lty);
   // Every per-element loop sits in one guarded block with in-bounds
   // (clamped) addresses, so its loads are issued together rather than one
   // round trip per element.  With R = 16 the column is read from HBM once:
@@ -398,14 +391,14 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
 #pragma unroll
     for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
-      const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * kX1Tile];
+      const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) << ltx];
       v[j] = s < n ? xv : make_double2(0.0, 0.0);
       if constexpr (R == 16) o[j] = v[j];
     }
   }
   // even frequencies
   fft_regs_r<LOGNH, R>(v, buf, -1);
-  if (pack && c == 0) {
+  if (packed) {
     packed_product<R>(v, buf, he, Hh + (int64_t)C * (2 * Nh), Nh, 0, Ta, per);
   } else if (act) {
 #pragma unroll
@@ -418,14 +411,14 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
     for (int j = 0; j < per; ++j) {
       const int s = t + Ta * j;
       if constexpr (R != 16) {
-        const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) * kX1Tile];
+        const double2 xv = xcol[(int64_t)(s < n ? n - 1 - s : 0) << ltx];
         o[j] = s < n ? xv : make_double2(0.0, 0.0);
       }
       o[j] = cmul(o[j], real_root(s, rs));
     }
   }
   fft_regs_r<LOGNH, R>(o, buf, -1);
-  if (pack && c == 0) {
+  if (packed) {
     packed_product<R>(o, buf, ho, Hh + (int64_t)C * (2 * Nh) + Nh, Nh, 1, Ta, per);
   } else if (act) {
 #pragma unroll
@@ -439,8 +432,8 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
       const int s = t + Ta * j;
       const double2 q = cmul(o[j], conj2(real_root(s, rs)));
       const int ra = s - (n - 1), rb = s + Nh - (n - 1);
-      if (ra >= 0 && ra < n) ycol[(int64_t)ra * kY1Tile] = cadd(v[j], q);
-      if (rb >= 0 && rb < n) ycol[(int64_t)rb * kY1Tile] = csub(v[j], q);
+      if (ra >= 0 && ra < n) ycol[(int64_t)ra << lty] = cadd(v[j], q);
+      if (rb >= 0 && rb < n) ycol[(int64_t)rb << lty] = csub(v[j], q);
     }
   }
 }
@@ -455,7 +448,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_cols_pass(
 template <int LOGM, int R>
 __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
     const double2* __restrict__ Y1, int n, int L, int w, int P, int W, int out_reverse,
-    int carry_off, int pack, uint64_t* __restrict__ y, DevStatus* st) {
+    int carry_off, int pack, int lt, uint64_t* __restrict__ y, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint32_t red[32];
   __shared__ RowStatus rst;
@@ -476,7 +469,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
 #pragma unroll
     for (int j = 0; j < per; ++j) {
       const int k = t + Ta * j;
-      v[j] = Y1[tidx<kY1Tile>(k, i, n)];
+      v[j] = Y1[tidx(k, i, n, lt)];
       wk[j] = conj2(real_root(k, rs));
     }
     // packed: column 0 holds Y[0] + i Y[M] (both real); otherwise Y[M] is
@@ -486,7 +479,7 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
         ytop = make_double2(v[0].y, 0.0);
         v[0] = make_double2(v[0].x, 0.0);
       } else {
-        ytop = Y1[tidx<kY1Tile>(M, i, n)];
+        ytop = Y1[tidx(M, i, n, lt)];
       }
     }
 #pragma unroll
@@ -556,11 +549,11 @@ __global__ void __launch_bounds__(512, (R == 8 ? 4 : 2)) k_rows_inv(
 __host__ __device__ constexpr int rows3_threads(int K) { return K / 8 < 64 ? 64 : K / 8; }
 
 // One row of the forward pass (row r of `in`, spectrum row r of `out` in
-// tiles of TW columns); blockDim.x = rows3_threads(K).
-template <int LOGK, int TW>
+// tiles of 2^lt columns); blockDim.x = rows3_threads(K).
+template <int LOGK>
 __device__ __forceinline__ void row_fwd3(const uint64_t* __restrict__ in, int W, int P, int w,
                                          int L, int gather_n, double2* __restrict__ out,
-                                         int rows_alloc, int r, int pack, double2* buf,
+                                         int rows_alloc, int r, int pack, int lt, double2* buf,
                                          uint32_t* red, DevStatus* st) {
   constexpr int K = 1 << LOGK, KA = K / 2, T = rows3_threads(K), S = K / T;
   const int t = threadIdx.x;
@@ -603,31 +596,31 @@ __device__ __forceinline__ void row_fwd3(const uint64_t* __restrict__ in, int W,
   }
   __syncthreads();
   fft_pair_lds<LOGK - 1, LOGK, T>(bufA, bufB, -1);
-  if (pack) pack_real_row<TW, true>(bufA, KA, out, r, rows_alloc);
-  else pack_real_row<TW, false>(bufA, KA, out, r, rows_alloc);
+  if (pack) pack_real_row<true>(bufA, KA, out, r, rows_alloc, lt);
+  else pack_real_row<false>(bufA, KA, out, r, rows_alloc, lt);
   const int b0 = pack ? KA : KA + 1;           // first column of the bins 3m+1
-  for (int m = t; m < K; m += T) out[tidx<TW>(b0 + m, r, rows_alloc)] = bufB[lds_slot(m)];
+  for (int m = t; m < K; m += T) out[tidx(b0 + m, r, rows_alloc, lt)] = bufB[lds_slot(m)];
 }
 
 template <int LOGK>
 __global__ void __launch_bounds__(256) k_rows_fwd3(const uint64_t* __restrict__ in, int W, int P,
                                                    int w, int L, int count, int gather_n,
                                                    double2* __restrict__ out, int rows_alloc,
-                                                   int pack, DevStatus* st) {
+                                                   int pack, int lt, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint32_t red[32];
   const int r = xcd_slot(blockIdx.x, gridDim.x);
   if (r >= count) return;
-  row_fwd3<LOGK, kX1Tile>(in, W, P, w, L, gather_n, out, rows_alloc, r, pack, buf, red, st);
+  row_fwd3<LOGK>(in, W, P, w, L, gather_n, out, rows_alloc, r, pack, lt, buf, red, st);
 }
 
 // One row of the inverse pass (spectrum row i of the n rows of Y1 in tiles
-// of TW columns; output row out_row(i, out_reverse)); blockDim.x =
+// of 2^lt columns; output row out_row(i, out_reverse)); blockDim.x =
 // rows3_threads(K).
-template <int LOGK, int TW>
+template <int LOGK>
 __device__ __forceinline__ void row_inv3(const double2* __restrict__ Y1, int n, int L, int w,
                                          int P, int W, int out_reverse, int carry_off, int pack,
-                                         uint64_t* __restrict__ y, int i, double2* buf,
+                                         int lt, uint64_t* __restrict__ y, int i, double2* buf,
                                          uint32_t* red, DevStatus* st) {
   __shared__ RowStatus rst;
   __shared__ double2 ytop;                 // bin 3(K/2) (packed: the imaginary part of column 0)
@@ -647,16 +640,16 @@ __device__ __forceinline__ void row_inv3(const double2* __restrict__ Y1, int n, 
 #pragma unroll
     for (int j = 0; j < SA; ++j) {
       const int k = t + T * j;
-      va[j] = Y1[tidx<TW>(k < KA ? k : 0, i, n)];
+      va[j] = Y1[tidx(k < KA ? k : 0, i, n, lt)];
     }
 #pragma unroll
-    for (int j = 0; j < S; ++j) vb[j] = Y1[tidx<TW>(b0 + t + T * j, i, n)];
+    for (int j = 0; j < S; ++j) vb[j] = Y1[tidx(b0 + t + T * j, i, n, lt)];
     if (t == 0) {
       if (pack) {
         ytop = make_double2(va[0].y, 0.0);
         va[0] = make_double2(va[0].x, 0.0);
       } else {
-        ytop = Y1[tidx<TW>(KA, i, n)];
+        ytop = Y1[tidx(KA, i, n, lt)];
       }
     }
 #pragma unroll
@@ -733,13 +726,13 @@ __device__ __forceinline__ void row_inv3(const double2* __restrict__ Y1, int n, 
 template <int LOGK>
 __global__ void __launch_bounds__(256) k_rows_inv3(const double2* __restrict__ Y1, int n, int L,
                                                    int w, int P, int W, int out_reverse,
-                                                   int carry_off, int pack,
+                                                   int carry_off, int pack, int lt,
                                                    uint64_t* __restrict__ y, DevStatus* st) {
   extern __shared__ double2 buf[];
   __shared__ uint32_t red[32];
   const int i = xcd_slot(blockIdx.x, gridDim.x);
   if (i >= n) return;
-  row_inv3<LOGK, kY1Tile>(Y1, n, L, w, P, W, out_reverse, carry_off, pack, y, i, buf, red, st);
+  row_inv3<LOGK>(Y1, n, L, w, P, W, out_reverse, carry_off, pack, lt, y, i, buf, red, st);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -783,7 +776,8 @@ hipError_t launch_h_norms(const uint64_t* h, int W, int P, int rows, int gather_
 
 template <int LOGM>
 hipError_t rows_fwd_t(const uint64_t* in, int W, int P, int w, int L, int count, int gather_n,
-                      double2* out, int rows_alloc, int pack, DevStatus* st, hipStream_t s) {
+                      double2* out, int rows_alloc, int pack, int lt, DevStatus* st,
+                      hipStream_t s) {
   constexpr int M = 1 << LOGM;
   const int T = fft_threads(M, 16);           // the LDS transform needs N/16 threads
   const size_t lds = sizeof(double2) * (size_t)lds_points(M);
@@ -791,16 +785,17 @@ hipError_t rows_fwd_t(const uint64_t* in, int W, int P, int w, int L, int count,
   if (e != hipSuccess) return e;
   const int grid = (count + 7) / 8 * 8;         // xcd_slot needs a multiple of 8
   hipLaunchKernelGGL(k_rows_fwd<LOGM>, dim3(grid), dim3(T), lds, s, in, W, P, w, L, count,
-                     gather_n, out, rows_alloc, pack, st);
+                     gather_n, out, rows_alloc, pack, lt, st);
   return hipGetLastError();
 }
 
 hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int count,
-                           int gather_n, int logM, double2* out, int rows_alloc, int pack,
+                           int gather_n, int logM, double2* out, int rows_alloc, int pack, int lt,
                            DevStatus* st, hipStream_t s) {
   switch (logM) {
 #define HMV_RF(k) \
-  case k: return rows_fwd_t<k>(in, W, P, w, L, count, gather_n, out, rows_alloc, pack, st, s);
+  case k:         \
+    return rows_fwd_t<k>(in, W, P, w, L, count, gather_n, out, rows_alloc, pack, lt, st, s);
     HMV_RF(1) HMV_RF(2) HMV_RF(3) HMV_RF(4) HMV_RF(5) HMV_RF(6) HMV_RF(7) HMV_RF(8) HMV_RF(9)
     HMV_RF(10) HMV_RF(11) HMV_RF(12)
 #undef HMV_RF
@@ -810,23 +805,25 @@ hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int c
 
 template <int LOGK>
 hipError_t rows_fwd3_t(const uint64_t* in, int W, int P, int w, int L, int count, int gather_n,
-                       double2* out, int rows_alloc, int pack, DevStatus* st, hipStream_t s) {
+                       double2* out, int rows_alloc, int pack, int lt, DevStatus* st,
+                       hipStream_t s) {
   constexpr int K = 1 << LOGK;
   const size_t lds = sizeof(double2) * (size_t)(lds_points(K / 2) + lds_points(K));
   hipError_t e = set_lds((const void*)k_rows_fwd3<LOGK>, lds);
   if (e != hipSuccess) return e;
   const int grid = (count + 7) / 8 * 8;         // xcd_slot needs a multiple of 8
   hipLaunchKernelGGL(k_rows_fwd3<LOGK>, dim3(grid), dim3(rows3_threads(K)), lds, s, in, W, P, w,
-                     L, count, gather_n, out, rows_alloc, pack, st);
+                     L, count, gather_n, out, rows_alloc, pack, lt, st);
   return hipGetLastError();
 }
 
 hipError_t launch_rows_fwd3(const uint64_t* in, int W, int P, int w, int L, int count,
-                            int gather_n, int logK, double2* out, int rows_alloc, int pack,
+                            int gather_n, int logK, double2* out, int rows_alloc, int pack, int lt,
                             DevStatus* st, hipStream_t s) {
   switch (logK) {
 #define HMV_RF3(k) \
-  case k: return rows_fwd3_t<k>(in, W, P, w, L, count, gather_n, out, rows_alloc, pack, st, s);
+  case k:          \
+    return rows_fwd3_t<k>(in, W, P, w, L, count, gather_n, out, rows_alloc, pack, lt, st, s);
     HMV_RF3(6) HMV_RF3(7) HMV_RF3(8) HMV_RF3(9) HMV_RF3(10) HMV_RF3(11)
 #undef HMV_RF3
     default: return hipErrorInvalidValue;
@@ -834,26 +831,26 @@ hipError_t launch_rows_fwd3(const uint64_t* in, int W, int P, int w, int L, int 
 }
 
 template <int LOGNH>
-hipError_t cols_plan_t(const double2* H1, int rows, int C, double scale, int pack, double2* Hh,
-                       hipStream_t s) {
+hipError_t cols_plan_t(const double2* H1, int rows, int C, double scale, int pack, int lt,
+                       double2* Hh, hipStream_t s) {
   const size_t lds = sizeof(double2) * (size_t)lds_points(1 << LOGNH);
   hipError_t e = set_lds((const void*)k_cols_plan<LOGNH>, lds);
   if (e != hipSuccess) return e;
   const int grid = (C + 7) / 8 * 8;
   hipLaunchKernelGGL(k_cols_plan<LOGNH>, dim3(grid), dim3(fft_threads(1 << LOGNH, 16)), lds, s, H1,
-                     rows, C, scale, pack, Hh);
+                     rows, C, scale, pack, lt, Hh);
   return hipGetLastError();
 }
 
 template <int LOGNH, int R>
 hipError_t cols_pass_r(const double2* X1, const double2* Hh, int n, int C, int linear, int pack,
-                       int kvec, double2* Y1, hipStream_t s) {
+                       int kvec, int ltx, int lty, double2* Y1, hipStream_t s) {
   const size_t lds = sizeof(double2) * (size_t)lds_points(1 << LOGNH);
   hipError_t e = set_lds((const void*)k_cols_pass<LOGNH, R>, lds);
   if (e != hipSuccess) return e;
   const int grid = (C + 7) / 8 * 8 * kvec;    // xcd_slot needs a multiple of 8 per vector
   hipLaunchKernelGGL((k_cols_pass<LOGNH, R>), dim3(grid), dim3(fft_threads(1 << LOGNH, R)), lds,
-                     s, X1, Hh, n, C, linear, pack, kvec, Y1);
+                     s, X1, Hh, n, C, linear, pack, kvec, ltx, lty, Y1);
   return hipGetLastError();
 }
 
@@ -861,12 +858,13 @@ hipError_t cols_pass_r(const double2* X1, const double2* Hh, int n, int C, int l
 // column order
 template <int LOGNH>
 hipError_t cols_pass_t(const double2* X1, const double2* Hh, int n, int C, int variant, int pack,
-                       int kvec, double2* Y1, hipStream_t s) {
+                       int kvec, int ltx, int lty, double2* Y1, hipStream_t s) {
   const int linear = (variant >> 1) & 1;
   if constexpr (has_radix8(LOGNH)) {
-    if (variant & 1) return cols_pass_r<LOGNH, 8>(X1, Hh, n, C, linear, pack, kvec, Y1, s);
+    if (variant & 1)
+      return cols_pass_r<LOGNH, 8>(X1, Hh, n, C, linear, pack, kvec, ltx, lty, Y1, s);
   }
-  return cols_pass_r<LOGNH, 16>(X1, Hh, n, C, linear, pack, kvec, Y1, s);
+  return cols_pass_r<LOGNH, 16>(X1, Hh, n, C, linear, pack, kvec, ltx, lty, Y1, s);
 }
 
 #define HMV_NT_DISPATCH(FN, ...)                  \
@@ -888,19 +886,21 @@ hipError_t cols_pass_t(const double2* X1, const double2* Hh, int n, int C, int v
   }
 
 hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, double scale,
-                            int pack, double2* Hh, hipStream_t s) {
-  HMV_NT_DISPATCH(cols_plan_t, H1, rows, C, scale, pack, Hh, s)
+                            int pack, int lt, double2* Hh, hipStream_t s) {
+  HMV_NT_DISPATCH(cols_plan_t, H1, rows, C, scale, pack, lt, Hh, s)
 }
 
 hipError_t launch_cols_pass(const double2* X1, const double2* Hh, int n, int C, int logNt,
-                            int pack, double2* Y1, int variant, hipStream_t s, int kvec) {
-  if (kvec < 1) return hipErrorInvalidValue;
-  HMV_NT_DISPATCH(cols_pass_t, X1, Hh, n, C, variant, pack, kvec, Y1, s)
+                            int pack, double2* Y1, int variant, int ltx, int lty, hipStream_t s,
+                            int kvec) {
+  if (kvec < 1 || ltx < 0 || ltx > kMaxTileLog || lty < 0 || lty > kMaxTileLog)
+    return hipErrorInvalidValue;
+  HMV_NT_DISPATCH(cols_pass_t, X1, Hh, n, C, variant, pack, kvec, ltx, lty, Y1, s)
 }
 
 template <int LOGM, int R>
 hipError_t rows_inv_r(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
-                      int pack, uint64_t* y, DevStatus* st, hipStream_t s) {
+                      int pack, int lt, uint64_t* y, DevStatus* st, hipStream_t s) {
   constexpr int M = 1 << LOGM;
   const int T = fft_threads(M, R);
   const int NC = 2 * L - 1;
@@ -914,26 +914,27 @@ hipError_t rows_inv_r(const double2* Y1, int n, int L, int w, int P, int W, int 
   if (e != hipSuccess) return e;
   const int grid = (n + 7) / 8 * 8;             // xcd_slot needs a multiple of 8
   hipLaunchKernelGGL((k_rows_inv<LOGM, R>), dim3(grid), dim3(T), lds, s, Y1, n, L, w, P, W,
-                     out_reverse, (int)carry_off, pack, y, st);
+                     out_reverse, (int)carry_off, pack, lt, y, st);
   return hipGetLastError();
 }
 
 // variant: bit 0 = radix-8 transform (where it exists)
 template <int LOGM>
 hipError_t rows_inv_t(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
-                      int pack, uint64_t* y, DevStatus* st, int variant, hipStream_t s) {
+                      int pack, int lt, uint64_t* y, DevStatus* st, int variant, hipStream_t s) {
   if constexpr (has_radix8(LOGM)) {
-    if (variant & 1) return rows_inv_r<LOGM, 8>(Y1, n, L, w, P, W, out_reverse, pack, y, st, s);
+    if (variant & 1)
+      return rows_inv_r<LOGM, 8>(Y1, n, L, w, P, W, out_reverse, pack, lt, y, st, s);
   }
-  return rows_inv_r<LOGM, 16>(Y1, n, L, w, P, W, out_reverse, pack, y, st, s);
+  return rows_inv_r<LOGM, 16>(Y1, n, L, w, P, W, out_reverse, pack, lt, y, st, s);
 }
 
 hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
-                           int out_reverse, int pack, uint64_t* y, DevStatus* st, int variant,
-                           hipStream_t s) {
+                           int out_reverse, int pack, int lt, uint64_t* y, DevStatus* st,
+                           int variant, hipStream_t s) {
   switch (logM) {
 #define HMV_RI(k) \
-  case k: return rows_inv_t<k>(Y1, n, L, w, P, W, out_reverse, pack, y, st, variant, s);
+  case k: return rows_inv_t<k>(Y1, n, L, w, P, W, out_reverse, pack, lt, y, st, variant, s);
     HMV_RI(1) HMV_RI(2) HMV_RI(3) HMV_RI(4) HMV_RI(5) HMV_RI(6) HMV_RI(7) HMV_RI(8) HMV_RI(9)
     HMV_RI(10) HMV_RI(11) HMV_RI(12)
 #undef HMV_RI
@@ -943,7 +944,7 @@ hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int
 
 template <int LOGK>
 hipError_t rows_inv3_t(const double2* Y1, int n, int L, int w, int P, int W, int out_reverse,
-                       int pack, uint64_t* y, DevStatus* st, hipStream_t s) {
+                       int pack, int lt, uint64_t* y, DevStatus* st, hipStream_t s) {
   constexpr int K = 1 << LOGK;
   const int T = rows3_threads(K);
   const int NC = 2 * L - 1;
@@ -957,16 +958,16 @@ hipError_t rows_inv3_t(const double2* Y1, int n, int L, int w, int P, int W, int
   if (e != hipSuccess) return e;
   const int grid = (n + 7) / 8 * 8;             // xcd_slot needs a multiple of 8
   hipLaunchKernelGGL(k_rows_inv3<LOGK>, dim3(grid), dim3(T), lds, s, Y1, n, L, w, P, W,
-                     out_reverse, (int)carry_off, pack, y, st);
+                     out_reverse, (int)carry_off, pack, lt, y, st);
   return hipGetLastError();
 }
 
 hipError_t launch_rows_inv3(const double2* Y1, int n, int logK, int L, int w, int P, int W,
-                            int out_reverse, int pack, uint64_t* y, DevStatus* st,
+                            int out_reverse, int pack, int lt, uint64_t* y, DevStatus* st,
                             hipStream_t s) {
   switch (logK) {
 #define HMV_RI3(k) \
-  case k: return rows_inv3_t<k>(Y1, n, L, w, P, W, out_reverse, pack, y, st, s);
+  case k: return rows_inv3_t<k>(Y1, n, L, w, P, W, out_reverse, pack, lt, y, st, s);
     HMV_RI3(6) HMV_RI3(7) HMV_RI3(8) HMV_RI3(9) HMV_RI3(10) HMV_RI3(11)
 #undef HMV_RI3
     default: return hipErrorInvalidValue;
@@ -1050,7 +1051,7 @@ __device__ __forceinline__ void b_row_fwd(const uint64_t* in, int W, int P, int 
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
   fft_lds(buf, logM, -1);
-  pack_real_row<8>(buf, M, out, r, rows_alloc);
+  pack_real_row<false>(buf, M, out, r, rows_alloc, 3);
   __syncthreads();
 }
 
@@ -1346,9 +1347,9 @@ __global__ void __launch_bounds__(256) k_batch_rows_fwd3(const BatchInst* __rest
   const BatchInst I = inst[d.x];
   const int rows_h = 2 * I.n - 1;
   if (d.z < rows_h)
-    row_fwd3<LOGK, 8>(I.h, I.W, I.P, I.w, I.L, I.gather, I.H1, rows_h, d.z, 0, buf, red, st);
+    row_fwd3<LOGK>(I.h, I.W, I.P, I.w, I.L, I.gather, I.H1, rows_h, d.z, 0, 3, buf, red, st);
   else
-    row_fwd3<LOGK, 8>(I.x, I.W, I.P, I.w, I.L, 0, I.X1, I.n, d.z - rows_h, 0, buf, red, st);
+    row_fwd3<LOGK>(I.x, I.W, I.P, I.w, I.L, 0, I.X1, I.n, d.z - rows_h, 0, 3, buf, red, st);
 }
 
 template <int LOGK>
@@ -1365,8 +1366,8 @@ __global__ void __launch_bounds__(256) k_batch_rows_inv3(const BatchInst* __rest
   // carry scratch follows it
   constexpr int K = 1 << LOGK;
   const int carry_off = (int)sizeof(double2) * (lds_points(K / 2) + lds_points(K));
-  row_inv3<LOGK, 8>(I.Y1, I.n, I.L, I.w, I.P, I.W, I.reverse, carry_off, 0, I.y, d.z, buf, red,
-                    st);
+  row_inv3<LOGK>(I.Y1, I.n, I.L, I.w, I.P, I.W, I.reverse, carry_off, 0, 3, I.y, d.z, buf, red,
+                 st);
 }
 
 template <int LOGK>

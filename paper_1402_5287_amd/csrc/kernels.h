@@ -10,8 +10,8 @@ namespace hmv {
 struct DevStatus;
 
 constexpr int kMaxWords = 648;      // W for P up to 40960 is 641
-constexpr int kSchoolMaxK = 16;      // coefficients per thread in the schoolbook row kernel
-constexpr int kSchoolThreads = 512;  // work-group size of the schoolbook row kernel
+constexpr int kSchoolMaxK = 16;      // outputs per thread of the schoolbook kernel, at most
+constexpr int kSchoolThreads = 512;  // work-group size of the schoolbook kernel
 constexpr int kBatchThreads = 256;   // work-group size of the single-launch batch kernel
 
 // status block
@@ -35,30 +35,33 @@ hipError_t fft_tables_init();
 hipError_t launch_h_norms(const uint64_t* h, int W, int P, int rows, int gather_n, int wlo,
                           int whi, unsigned long long* norms, DevStatus* st, hipStream_t s);
 // pack = 1: the two real limb bins share spectrum column 0 (C = N_z/2
-// columns, the resident spectrum one more); pack = 0: C = N_z/2 + 1
+// columns, the resident spectrum one more); pack = 0: C = N_z/2 + 1.
+// lt, ltx, lty: log2 of the tile width of a row spectrum (tidx), 0..kMaxTileLog
+constexpr int kMaxTileLog = 3;
 hipError_t launch_rows_fwd(const uint64_t* in, int W, int P, int w, int L, int count,
-                           int gather_n, int logM, double2* out, int rows_alloc, int pack,
+                           int gather_n, int logM, double2* out, int rows_alloc, int pack, int lt,
                            DevStatus* st, hipStream_t s);
 hipError_t launch_cols_plan(const double2* H1, int rows, int C, int logNt, double scale,
-                            int pack, double2* Hh, hipStream_t s);
+                            int pack, int lt, double2* Hh, hipStream_t s);
 // variant bit 0: radix-8 register transforms (where they exist, 8^k points);
 // bit 1 (column pass only): linear instead of XCD-grouped column order.
 constexpr int kColsVariants = 4, kRowsInvVariants = 2;
 // kvec vectors: X1 and Y1 hold kvec n rows, vector v in rows v n .. v n + n - 1
 hipError_t launch_cols_pass(const double2* X1, const double2* Hh, int n, int C, int logNt,
-                            int pack, double2* Y1, int variant, hipStream_t s, int kvec = 1);
+                            int pack, double2* Y1, int variant, int ltx, int lty, hipStream_t s,
+                            int kvec = 1);
 // inverse row passes: n rows of Y1; out_reverse = 0 writes spectrum row i to
 // output row i, out_reverse = m > 0 reverses the rows within each block of m
 hipError_t launch_rows_inv(const double2* Y1, int n, int logM, int L, int w, int P, int W,
-                           int out_reverse, int pack, uint64_t* y, DevStatus* st, int variant,
-                           hipStream_t s);
+                           int out_reverse, int pack, int lt, uint64_t* y, DevStatus* st,
+                           int variant, hipStream_t s);
 // limb transforms of 3K = 3 * 2^logK points, 6 <= logK <= kR3MaxLogK (one
 // launch variant each)
 hipError_t launch_rows_fwd3(const uint64_t* in, int W, int P, int w, int L, int count,
-                            int gather_n, int logK, double2* out, int rows_alloc, int pack,
+                            int gather_n, int logK, double2* out, int rows_alloc, int pack, int lt,
                             DevStatus* st, hipStream_t s);
 hipError_t launch_rows_inv3(const double2* Y1, int n, int logK, int L, int w, int P, int W,
-                            int out_reverse, int pack, uint64_t* y, DevStatus* st,
+                            int out_reverse, int pack, int lt, uint64_t* y, DevStatus* st,
                             hipStream_t s);
 
 }  // namespace hmv

@@ -102,15 +102,24 @@ double fft_bound_for(const FftSizes& z, int64_t n, double norm_h, int pack) {
 // ------------------------------------------------------------------ split-FFT
 namespace {
 
-// Launch-variant tuning.  For each shape the planner times every variant of
-// the column pass and of the inverse row pass (kernels.h) on the plan's own
-// data and keeps the fastest; results are cached per (device, n, P, w), so
-// later plans of a shape (and one-shot calls) reuse them.
+// Launch tuning.  For each shape the planner times, on the plan's own data,
+// every combination of the spectrum tile widths (2, 4 or 8 bins for the
+// spectra of x and of y) and the launch variants of the column pass and of
+// the inverse row pass (kernels.h) over one whole matvec pipeline; the four
+// fastest and the untuned default are timed again in interleaved rounds, and
+// a choice replaces the default only if it is more than 1 % faster.  Results
+// are cached per (device, n, P, w), so later plans of a shape (and one-shot
+// calls) reuse them.
+struct TuneChoice {
+  int cols_variant, rows_inv_variant, ltx, lty;
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int64_t, int32_t, int>, std::pair<int, int>> g_tune_cache;
+std::map<std::tuple<int, int64_t, int32_t, int>, TuneChoice> g_tune_cache;
 int g_autotune = 1;
 int g_force_cols = -1, g_force_rinv = -1;       // tests: fixed variants (-1 = tune)
 int g_force_z3 = -1, g_force_pack = -1;         // tests: fixed spectrum layout (-1 = auto)
+int g_force_ltx = -1, g_force_lty = -1;         // tests: fixed tile widths (-1 = tune)
+constexpr int kDefaultTileLog = 2;              // 4 bins per tile when not tuned
 
 bool radix8_ok(int logn) { return logn == 6 || logn == 9 || logn == 12; }
 
@@ -128,64 +137,124 @@ hipError_t time_launches(F launch, int reps, hipEvent_t a, hipEvent_t b, hipStre
   return e;
 }
 
-// Times the variants with the row spectra of h (first n rows of the plan
-// scratch) as x's spectra; the outputs are discarded and the status block
-// is cleared afterwards.  Without may_run (one-shot calls) a shape that has
-// not been tuned keeps the first variants.
-int fft_tune(hmv_plan* p, DevStatus* st, char* scratch, bool may_run, hipStream_t s) {
+void apply_forced(hmv_plan* p) {
+  if (g_force_cols >= 0) p->cols_variant = g_force_cols;
+  if (g_force_rinv >= 0) p->rows_inv_variant = p->z3 ? 0 : g_force_rinv;
+  if (g_force_ltx >= 0) p->ltx = g_force_ltx;
+  if (g_force_lty >= 0) p->lty = g_force_lty;
+}
+
+// The first n rows of h stand in for x (valid inputs of the same shape); the
+// outputs are discarded and the status block is cleared afterwards.
+// Without may_run (one-shot calls) a shape that has not been tuned keeps
+// the first variants and the default tile widths.
+int fft_tune(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch, bool may_run,
+             hipStream_t s) {
+  p->cols_variant = 0;
+  p->rows_inv_variant = 0;
+  p->ltx = p->lty = kDefaultTileLog;
+  if (!g_autotune) {
+    apply_forced(p);
+    return HMV_OK;
+  }
   const std::tuple<int, int64_t, int32_t, int> key{p->device, p->n, p->P, p->w};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      p->cols_variant = it->second.first;
-      p->rows_inv_variant = it->second.second;
+      p->cols_variant = it->second.cols_variant;
+      p->rows_inv_variant = it->second.rows_inv_variant;
+      p->ltx = it->second.ltx;
+      p->lty = it->second.lty;
+      apply_forced(p);
       return HMV_OK;
     }
   }
-  if (!may_run) return HMV_OK;
+  if (!may_run) {
+    apply_forced(p);
+    return HMV_OK;
+  }
   const int n = (int)p->n, W = (int)words_of(p->P);
   double2* X1 = reinterpret_cast<double2*>(scratch + align_up(kNormSlots * 8));
   double2* Y1 = X1 + align_up(16 * 8 * int64_t(p->tiles) * n) / 16;
   uint64_t* yt = reinterpret_cast<uint64_t*>(X1);      // x's spectra are no longer needed then
+  auto fwd = [&](int ltx) {
+    return p->z3 ? launch_rows_fwd3(h, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, p->pack, ltx,
+                                    st, s)
+                 : launch_rows_fwd(h, W, p->P, p->w, p->L, n, 0, p->logM, X1, n, p->pack, ltx,
+                                   st, s);
+  };
+  auto inv = [&](int lty, int v) {
+    return p->z3 ? launch_rows_inv3(Y1, n, p->logM, p->L, p->w, p->P, W, 0, p->pack, lty, yt, st,
+                                    s)
+                 : launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, 0, p->pack, lty, yt, st,
+                                   v, s);
+  };
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e = hipEventCreate(&a);
   if (e == hipSuccess) e = hipEventCreate(&b);
-  int bc = 0, br = 0;
-  float best = 0.0f;
-  for (int v = 0; v < kColsVariants && e == hipSuccess; ++v) {
-    if ((v & 1) && !radix8_ok(p->logNt - 1)) continue;
-    float ms = 0.0f;
-    e = time_launches(
-        [&] { return launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, p->pack, Y1, v, s); }, 2, a,
-        b, s, &ms);
-    if (e == hipSuccess && (v == 0 || ms < best)) {
-      best = ms;
-      bc = v;
-    }
+  // every choice, timed over a whole matvec pipeline (forward rows, column
+  // pass, inverse rows)
+  std::vector<TuneChoice> cand;
+  for (int lx = 1; lx <= kMaxTileLog; ++lx)
+    for (int ly = 1; ly <= kMaxTileLog; ++ly)
+      for (int cv = 0; cv < kColsVariants; ++cv) {
+        if ((cv & 1) && !radix8_ok(p->logNt - 1)) continue;
+        for (int rv = 0; rv < kRowsInvVariants; ++rv) {
+          if ((rv & 1) && (p->z3 || !radix8_ok(p->logM))) continue;
+          cand.push_back({cv, rv, lx, ly});
+        }
+      }
+  auto pipeline = [&](const TuneChoice& c) {
+    hipError_t r = fwd(c.ltx);
+    if (r == hipSuccess)
+      r = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, p->pack, Y1, c.cols_variant, c.ltx,
+                           c.lty, s);
+    if (r == hipSuccess) r = inv(c.lty, c.rows_inv_variant);
+    return r;
+  };
+  std::vector<float> t1(cand.size(), 0.0f);
+  for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k)
+    e = time_launches([&] { return pipeline(cand[k]); }, 2, a, b, s, &t1[k]);
+  // the four fastest and the untuned default, re-timed in interleaved rounds
+  std::vector<size_t> order(cand.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+  std::sort(order.begin(), order.end(), [&](size_t u, size_t v) { return t1[u] < t1[v]; });
+  std::vector<TuneChoice> fin;
+  fin.push_back({0, 0, kDefaultTileLog, kDefaultTileLog});
+  for (size_t k = 0; k < order.size() && fin.size() < 5; ++k) {
+    const TuneChoice& c = cand[order[k]];
+    if (c.cols_variant == 0 && c.rows_inv_variant == 0 && c.ltx == kDefaultTileLog &&
+        c.lty == kDefaultTileLog)
+      continue;
+    fin.push_back(c);
   }
-  for (int v = 0; v < kRowsInvVariants && e == hipSuccess && !p->z3; ++v) {
-    if ((v & 1) && !radix8_ok(p->logM)) continue;
-    float ms = 0.0f;
-    e = time_launches(
-        [&] {
-          return launch_rows_inv(Y1, n, p->logM, p->L, p->w, p->P, W, 0, p->pack, yt, st, v, s);
-        },
-        2,
-        a, b, s, &ms);
-    if (e == hipSuccess && (v == 0 || ms < best)) {
-      best = ms;
-      br = v;
+  std::vector<float> t2(fin.size(), 0.0f);
+  for (int round = 0; round < 3 && e == hipSuccess; ++round)
+    for (size_t k = 0; k < fin.size() && e == hipSuccess; ++k) {
+      float ms = 0.0f;
+      e = time_launches([&] { return pipeline(fin[k]); }, 3, a, b, s, &ms);
+      t2[k] += ms;
     }
-  }
+  // the default unless a choice beats it by more than 1 %
+  size_t best = 0;
+  for (size_t k = 1; k < fin.size(); ++k)
+    if (t2[k] < t2[best] && t2[k] < 0.99f * t2[0]) best = k;
+  const int bc = fin[best].cols_variant, br = fin[best].rows_inv_variant;
+  const int bx = fin[best].ltx, by = fin[best].lty;
   if (e == hipSuccess) e = launch_clear_status(st, s);
   if (a) (void)hipEventDestroy(a);
   if (b) (void)hipEventDestroy(b);
   if (e != hipSuccess) return status_from_hip(e, "tuning runs");
   p->cols_variant = bc;
   p->rows_inv_variant = br;
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune_cache[key] = {bc, br};
+  p->ltx = bx;
+  p->lty = by;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {bc, br, bx, by};
+  }
+  apply_forced(p);
   return HMV_OK;
 }
 
@@ -269,22 +338,19 @@ int fft_plan_build(hmv_plan* p, const uint64_t* h, DevStatus* st, char* scratch,
   p->Hh = reinterpret_cast<double2*>(plan_mem);
   // 3. forward 2-D transform of h, kept in the plan
   double2* H1 = reinterpret_cast<double2*>(h1mem);
-  e = z.z3 ? launch_rows_fwd3(h, W, P, z.w, z.L, rows, gather, z.logM, H1, rows, pack, st, s)
-           : launch_rows_fwd(h, W, P, z.w, z.L, rows, gather, z.logM, H1, rows, pack, st, s);
+  e = z.z3 ? launch_rows_fwd3(h, W, P, z.w, z.L, rows, gather, z.logM, H1, rows, pack,
+                              kDefaultTileLog, st, s)
+           : launch_rows_fwd(h, W, P, z.w, z.L, rows, gather, z.logM, H1, rows, pack,
+                             kDefaultTileLog, st, s);
   if (e != hipSuccess) return status_from_hip(e, "rows fwd (h)");
   // 1 / (N_t N_z): a power of two, or for N_z = 3K one rounding of 1/3
   const double scale = z.z3 ? std::ldexp(1.0 / 3.0, -(z.logNt + z.logM))
                             : std::ldexp(1.0, -(z.logNt + z.logM + 1));
-  e = launch_cols_plan(H1, rows, p->C, z.logNt, scale, pack, p->Hh, s);
+  e = launch_cols_plan(H1, rows, p->C, z.logNt, scale, pack, kDefaultTileLog, p->Hh, s);
   if (e != hipSuccess) return status_from_hip(e, "cols plan");
-  // 4. launch variants for this shape (h's spectra stand in for x's)
-  if (g_force_cols >= 0 || g_force_rinv >= 0) {
-    p->cols_variant = g_force_cols >= 0 ? g_force_cols : 0;
-    p->rows_inv_variant = g_force_rinv >= 0 && !z.z3 ? g_force_rinv : 0;
-    return HMV_OK;
-  }
-  if (g_autotune) return fft_tune(p, st, scratch, may_tune, s);
-  return HMV_OK;
+  // 4. tile widths and launch variants for this shape (h's first n rows
+  //    stand in for x)
+  return fft_tune(p, h, st, scratch, may_tune, s);
 }
 
 hipError_t mark(void* const* ev, int k, hipStream_t s) {
@@ -317,21 +383,24 @@ int fft_plan_matvec(const hmv_plan* p, const uint64_t* x, uint64_t* y, DevStatus
   hipError_t e = mark(ev, 0, s);
   if (e == hipSuccess)
     e = p->z3
-            ? launch_rows_fwd3(x, W, p->P, p->w, p->L, rows, 0, p->logM, X1, rows, p->pack, st, s)
-            : launch_rows_fwd(x, W, p->P, p->w, p->L, rows, 0, p->logM, X1, rows, p->pack, st, s);
+            ? launch_rows_fwd3(x, W, p->P, p->w, p->L, rows, 0, p->logM, X1, rows, p->pack,
+                               p->ltx, st, s)
+            : launch_rows_fwd(x, W, p->P, p->w, p->L, rows, 0, p->logM, X1, rows, p->pack,
+                              p->ltx, st, s);
   if (e != hipSuccess) return status_from_hip(e, "rows fwd (x)");
   e = mark(ev, 1, s);
   if (e == hipSuccess)
-    e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, p->pack, Y1, p->cols_variant, s, kvec);
+    e = launch_cols_pass(X1, p->Hh, n, p->C, p->logNt, p->pack, Y1, p->cols_variant, p->ltx,
+                         p->lty, s, kvec);
   if (e != hipSuccess) return status_from_hip(e, "cols pass");
   // Toeplitz and circulant outputs: each vector's rows reversed
   const int rev = (p->kind == HMV_HANKEL) ? 0 : n;
   e = mark(ev, 2, s);
   if (e == hipSuccess)
-    e = p->z3 ? launch_rows_inv3(Y1, rows, p->logM, p->L, p->w, Pout, Wout, rev, p->pack, y, st,
-                                 s)
-              : launch_rows_inv(Y1, rows, p->logM, p->L, p->w, Pout, Wout, rev, p->pack, y, st,
-                                p->rows_inv_variant, s);
+    e = p->z3 ? launch_rows_inv3(Y1, rows, p->logM, p->L, p->w, Pout, Wout, rev, p->pack, p->lty,
+                                 y, st, s)
+              : launch_rows_inv(Y1, rows, p->logM, p->L, p->w, Pout, Wout, rev, p->pack, p->lty,
+                                y, st, p->rows_inv_variant, s);
   if (e == hipSuccess) e = mark(ev, 3, s);
   return status_from_hip(e, "rows inv");
 }
@@ -878,6 +947,10 @@ int hmv_plan_info(const hmv_plan* p, hmv_plan_info_t* info) {
   info->cols_variant = p->cols_variant;
   info->rows_inv_variant = p->rows_inv_variant;
   info->spectrum_cols = p->C;
+  if (p->algo == HMV_SPLIT_FFT) {
+    info->x_tile = 1 << p->ltx;
+    info->y_tile = 1 << p->lty;
+  }
   return HMV_OK;
 }
 
@@ -887,6 +960,15 @@ int hmv_debug_force_variants(int32_t cols_variant, int32_t rows_inv_variant) {
     return HMV_EINVAL;
   g_force_cols = cols_variant;
   g_force_rinv = rows_inv_variant;
+  return HMV_OK;
+}
+
+int hmv_debug_force_tiles(int32_t x_tile, int32_t y_tile) {
+  auto lg = [](int32_t t) { return t == 2 ? 1 : t == 4 ? 2 : t == 8 ? 3 : -2; };
+  const int lx = x_tile == -1 ? -1 : lg(x_tile), ly = y_tile == -1 ? -1 : lg(y_tile);
+  if (lx == -2 || ly == -2) return HMV_EINVAL;
+  g_force_ltx = lx;
+  g_force_lty = ly;
   return HMV_OK;
 }
 

@@ -107,6 +107,7 @@ struct hmv_plan {
   int64_t plan_bytes_used = 0, mv_scratch = 0;
   double2* Hh = nullptr;           // resident spectrum of h (in caller plan memory)
   int cols_variant = 0, rows_inv_variant = 0;   // launch variants picked by the tuning runs
+  int ltx = 2, lty = 2;            // log2 tile widths of the spectra of x and of y
   // exact paths
   int logNz = 0;
   int64_t cols_padded = 0;

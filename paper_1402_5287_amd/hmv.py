@@ -55,6 +55,7 @@ SIGNATURES = {
                                        ctypes.POINTER(_vp)]),
     "hmv_debug_force_variants": (_c_int, [_c_i32, _c_i32]),
     "hmv_debug_force_layout": (_c_int, [_c_i32, _c_i32]),
+    "hmv_debug_force_tiles": (_c_int, [_c_i32, _c_i32]),
     "hmv_batch_launches": (_c_i32, [_vp, _c_i32]),
     "hmv_autotune": (_c_int, [_c_i32]),
     "hmv_plan_workspace_bytes": (_c_i64, [_vp]),
@@ -98,7 +99,8 @@ class PlanInfo(ctypes.Structure):
                 ("beta", ctypes.c_double), ("norm_h", ctypes.c_double),
                 ("plan_bytes", ctypes.c_int64), ("matvec_workspace_bytes", ctypes.c_int64),
                 ("cols_variant", ctypes.c_int32), ("rows_inv_variant", ctypes.c_int32),
-                ("spectrum_cols", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("spectrum_cols", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x_tile", ctypes.c_int32), ("y_tile", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -380,6 +382,12 @@ def force_layout(z3: int = -1, pack: int = -1) -> None:
     two limb transforms only; pack = 0 / 1: the two real limb bins in their
     own columns / sharing one; -1 = automatic)."""
     _check(lib().hmv_debug_force_layout(z3, pack), "force_layout")
+
+
+def force_tiles(x_tile: int = -1, y_tile: int = -1) -> None:
+    """Tests only: spectrum tile widths (2, 4 or 8 bins) of later split-FFT
+    plans for x and y (-1 = tuned)."""
+    _check(lib().hmv_debug_force_tiles(x_tile, y_tile), "force_tiles")
 
 
 def force_width(w: int) -> None:

@@ -309,6 +309,52 @@ def test_every_spectrum_layout_is_exact(n, P, expect3):
         assert (True, 0) in forms and (True, 1) in forms
 
 
+@pytest.mark.parametrize("n,P", [(200, 1500), (1000, 33220)])
+def test_every_tile_width_is_exact(n, P):
+    """Every pair of spectrum tile widths the tuner may pick (2, 4 or 8 bins
+    for the spectra of x and of y) gives the exact words, for a 3K and a
+    power-of-two limb transform, Hankel and Toeplitz."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    h = si.uniform(2 * n - 1, P, (76, n, P))
+    x = si.uniform(n, P, (77, n, P))
+    if n <= 300:
+        want = hankel.matvec_words("hankel", h, x, P)
+    elif kronecker.available():
+        want = kronecker.hankel_matvec_words(h, x, P)
+    else:
+        pytest.skip("GMP not available for the full-vector check")
+    hd, xd = hmv.to_device(h), hmv.to_device(x)
+    try:
+        for z3 in (0, 1):
+            for tx in (2, 4, 8):
+                for ty in (2, 4, 8):
+                    hmv.force_layout(z3, -1)
+                    hmv.force_tiles(tx, ty)
+                    for kind in ("hankel", "toeplitz"):
+                        plan = hmv.Plan(kind, hd, n, P, algo="split_fft")
+                        info = plan.info()
+                        assert (info["x_tile"], info["y_tile"]) == (tx, ty)
+                        announce("fft tiles", kind, n, P, z3, tx, ty, info["Nz"])
+                        y = torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda")
+                        plan.matvec(xd, y)
+                        rc, flags, _ = hmv.read_status(plan.ws)
+                        assert rc == 0 and flags == 0
+                        got = hmv.to_host(y)
+                        assert np.array_equal(got if kind == "hankel" else got[::-1], want), \
+                            (kind, z3, tx, ty)
+                        plan.close()
+    finally:
+        hmv.force_tiles(-1, -1)
+        hmv.force_layout(-1, -1)
+    plan = hmv.Plan("hankel", hd, n, P, algo="split_fft")
+    info = plan.info()
+    print("tuned tiles", info["x_tile"], info["y_tile"], "variants", info["cols_variant"],
+          info["rows_inv_variant"], flush=True)
+    assert info["x_tile"] in (2, 4, 8) and info["y_tile"] in (2, 4, 8)
+    plan.close()
+
+
 def test_graph_captured_planned_step():
     """A planned matvec at the session shape (n = 4096, P = 33220) captured in
     a HIP graph: three replays, each on a different x copied into the

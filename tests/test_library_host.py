@@ -115,4 +115,10 @@ def test_debug_switches_validate_and_restore():
     assert L.hmv_debug_force_layout(0, 1) == 0
     assert L.hmv_debug_force_layout(-1, -1) == 0
     assert L.hmv_debug_force_variants(4, 0) == hmv.EINVAL
+    assert L.hmv_debug_force_variants(0, 2) == hmv.EINVAL
     assert L.hmv_debug_force_variants(-1, -1) == 0
+    for bad in ((3, 4), (16, -1), (0, 1)):
+        assert L.hmv_debug_force_tiles(*bad) == hmv.EINVAL, bad
+    assert L.hmv_debug_force_tiles(8, 2) == 0
+    assert L.hmv_debug_force_tiles(-1, -1) == 0
+
