@@ -87,7 +87,7 @@ bool school_layout(int kind, int64_t n, int32_t P, SchoolLayout* lay) {
   if (w < 0) return false;
   lay->w = w;
   lay->L = limbs_of(P, w);
-  lay->ld = lay->L;
+  lay->ld = (lay->L + kSchoolMaxK + 1) & ~1;   // zero digits past L for the widened steps
   Carver c{nullptr, 0, INT64_MAX, true};
   c.take(kStatusBytes);
   lay->off_hd = align_up(c.off);
