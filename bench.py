@@ -587,6 +587,22 @@ def section_batch(dev, count=256, reps=3):
     e1.record()
     torch.cuda.synchronize()
     bms = _ms_between(e0, e1) / reps
+    # the same batch in one cooperative launch: timed, outputs compared
+    ref = [it[3].clone() for it in items]
+    batch_mb = ws.numel() / 2**20
+    _, batch_flags, _ = hmv.read_status(ws)
+    del ws
+    ws = hmv.workspace(hmv.batch_single_workspace_bytes(probs), device=dev)
+    single_mb = ws.numel() / 2**20
+    hmv.batch_matvec_single(probs, ws)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        hmv.batch_matvec_single(probs, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    one_ms = _ms_between(e0, e1) / reps
+    one_equal = all(torch.equal(r, it[3]) for r, it in zip(ref, items))
     # the same products one at a time (one-shot auto path), timed and compared
     single_ws = hmv.workspace(max(hmv.oneshot_workspace_bytes(k, n, P) for (k, _, _, _, n, P)
                                   in items), device=dev)
@@ -601,14 +617,19 @@ def section_batch(dev, count=256, reps=3):
     sms = _ms_between(e0, e1)
     equal = all(torch.equal(o, it[3]) for o, it in zip(outs, items))
     rc, flags, _ = hmv.read_status(ws)
+    flags |= batch_flags
     res = {"instances": count, "launches": hmv.batch_launches(probs), "batch_ms": round(bms, 3),
            "products_per_s": round(count / (bms * 1e-3), 1),
+           "one_launch_ms": round(one_ms, 3),
+           "one_launch_products_per_s": round(count / (one_ms * 1e-3), 1),
+           "one_launch_equal": bool(one_equal),
+           "one_launch_workspace_mb": round(single_mb, 1),
            "one_by_one_ms": round(sms, 3), "equal_to_single_path": bool(equal),
            "status_flags": flags,
            "kinds": [sum(1 for k, _, _ in inst if k == c) for c in range(3)],
-           "workspace_mb": round(ws.numel() / 2**20, 1)}
+           "workspace_mb": round(batch_mb, 1)}
     log(f"batch: {res}")
-    if not equal or flags:
+    if not equal or not one_equal or flags:
         raise SystemExit("batched products differ from the single path")
     return res
 

@@ -284,6 +284,20 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
                      void* stream);
 /* Number of kernel launches hmv_batch_matvec makes for these problems. */
 int32_t hmv_batch_launches(const hmv_problem* probs, int32_t count);
+/* The same products in ONE kernel launch (a cooperative launch: all its
+ * work-groups are resident together; the runtime refuses it otherwise and
+ * the call returns HMV_EDEVICE).  The work-groups take the items of each
+ * pass in turn and meet at a grid-wide barrier between passes; every item
+ * uses 256 threads and the limb transforms are of power-of-two size, so
+ * the workspace is larger (hmv_batch_single_workspace_bytes) and the batch
+ * slower than with hmv_batch_matvec.  Same arguments, limits, status block
+ * and synchronisation as hmv_batch_matvec; the outputs are identical.
+ * HMV_EINVAL for a batch with an instance whose power-of-two transforms do
+ * not fit one work-group's LDS.                                           */
+int64_t hmv_batch_single_workspace_bytes(const hmv_problem* probs, int32_t count);
+int hmv_batch_matvec_single(const hmv_problem* probs, int32_t count, void* ws, int64_t ws_bytes,
+                            void* stream);
+
 /* ---------------------------------------------------------------- serving
  * A request scheduler for sessions of planned matvecs (continuous
  * batching).  The caller provides one device pool (pool_bytes) from which

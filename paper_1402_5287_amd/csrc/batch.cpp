@@ -1,10 +1,12 @@
 // Batched launches: many independent (kind, n, P) products.  One launch
 // covers the work items of one pass whose transforms have the same size, for
 // every instance of that size (hmv_batch_launches counts them: 24 for the
-// 256-instance mix of four precisions).  Also the host-side sizing,
-// descriptors and item lists.  A single persistent launch with a device work
-// queue is kept in the source but switched off: it did not finish on two
-// runs and the cause is unknown.
+// 256-instance mix of four precisions).  hmv_batch_matvec_single runs the
+// whole batch as one cooperative launch with grid-wide barriers between the
+// passes.  Also the host-side sizing, descriptors and item lists.  A single
+// persistent launch with a device work queue and dependency counters is kept
+// in the source but switched off: it did not finish on two runs and the
+// cause is unknown.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,13 +37,13 @@ struct InstPlan {
 
 // Limb width of a batch instance from the worst-case bound (no data read):
 // every digit of h and x at magnitude 2^(w-1).
-// The row passes take limb transforms of 3 * 2^k points where those are
-// smaller (the persistent driver, switched off, has power-of-two rows only).
-bool batch_inst_sizes(int64_t n, int32_t P, FftSizes* out) {
+// With allow3 the row passes take limb transforms of 3 * 2^k points where
+// those are smaller; the single-launch forms have power-of-two rows only.
+bool batch_inst_sizes(int64_t n, int32_t P, bool allow3, FftSizes* out) {
   if (n < 1 || n > kBatchMaxN) return false;
   for (int w = kFftWMax; w >= kFftWMin; --w) {
     FftSizes z;
-    if (!fft_sizes(n, P, w, &z, !kBatchPersistent)) continue;
+    if (!fft_sizes(n, P, w, &z, allow3)) continue;
     const double nh = std::ldexp(1.0, w - 1) * std::sqrt((double)(2 * n - 1) * (double)z.L);
     const double nx = std::ldexp(1.0, w - 1) * std::sqrt((double)n * (double)z.L);
     // stages as for a plan without the shared column (fft_bound_for)
@@ -64,14 +66,14 @@ struct BatchLayout {
   std::vector<InstPlan> ip;
 };
 
-bool batch_layout(const hmv_problem* probs, int32_t count, BatchLayout* L) {
+bool batch_layout(const hmv_problem* probs, int32_t count, bool allow3, BatchLayout* L) {
   if (!probs || count < 1) return false;
   L->ip.resize(count);
   int64_t items = 0;
   for (int i = 0; i < count; ++i) {
     const hmv_problem& pr = probs[i];
     if (!valid_kind(pr.kind) || pr.P < 1 || pr.P > HMV_MAX_P) return false;
-    if (!batch_inst_sizes(pr.n, pr.P, &L->ip[i].z)) return false;
+    if (!batch_inst_sizes(pr.n, pr.P, allow3, &L->ip[i].z)) return false;
     items += 3 * pr.n - 1 + 2 * L->ip[i].z.C + pr.n;
   }
   if (items > INT32_MAX / 2) return false;
@@ -101,30 +103,17 @@ bool batch_layout(const hmv_problem* probs, int32_t count, BatchLayout* L) {
   return true;
 }
 
-}  // namespace
+// Status clear, instance descriptors and the pass-major item list, uploaded
+// into the workspace.  Within a pass the items are grouped by transform size
+// (largest first) and, inside a size, by instance cost.  runs gets one entry
+// per (pass, size); starts[p] is the first item of pass p.
+struct Run { int phase, logn, start, count; };
 
-extern "C" {
-
-int64_t hmv_batch_workspace_bytes(const hmv_problem* probs, int32_t count) {
-  BatchLayout L;
-  if (!batch_layout(probs, count, &L)) return HMV_EINVAL;
-  return L.total;
-}
-
-int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t ws_bytes,
-                     void* stream) {
-  BatchLayout L;
-  if (!batch_layout(probs, count, &L)) return HMV_EINVAL;
-  for (int i = 0; i < count; ++i)
-    if (!probs[i].h || !probs[i].x || !probs[i].y) return HMV_EINVAL;
-  if (!ws || ws_bytes < L.total) return HMV_ENOMEM;
-  clear_stale_error();
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
+int batch_prepare(const hmv_problem* probs, int32_t count, const BatchLayout& L, char* base,
+                  hipStream_t s, std::vector<Run>* runs, int starts[4]) {
   DevStatus* st = reinterpret_cast<DevStatus*>(base);
   hipError_t e = launch_clear_status(st, s);
   if (e != hipSuccess) return status_from_hip(e, "clear status");
-  // descriptors
   std::vector<BatchInst> inst(count);
   for (int i = 0; i < count; ++i) {
     const hmv_problem& pr = probs[i];
@@ -150,15 +139,12 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
     b.scale = z.z3 ? std::ldexp(1.0 / 3.0, -(z.logNt + z.logM))
                    : std::ldexp(1.0, -(z.logNt + z.logM + 1));
   }
-  // work items, phase-major; within a pass grouped by transform size (one
-  // launch per size), largest first
   std::vector<int> order(count);
   std::iota(order.begin(), order.end(), 0);
   std::vector<int4> items;
   items.reserve(L.nitems);
-  struct Run { int phase, logn, start, count; };
-  std::vector<Run> runs;
   for (int ph = 0; ph < 4; ++ph) {
+    starts[ph] = (int)items.size();
     auto logn_of = [&](int i) {
       const FftSizes& z = L.ip[i].z;
       return (ph == 0 || ph == 3) ? z.logM + (z.z3 ? kBatchLog3 : 0) : z.logNt - 1;
@@ -169,13 +155,13 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
     });
     for (int i : order) {
       const int logn = logn_of(i);
-      if (runs.empty() || runs.back().phase != ph || runs.back().logn != logn)
-        runs.push_back({ph, logn, (int)items.size(), 0});
+      if (runs->empty() || runs->back().phase != ph || runs->back().logn != logn)
+        runs->push_back({ph, logn, (int)items.size(), 0});
       const int cnt = ph == 0 ? 3 * (int)probs[i].n - 1
                       : ph == 3 ? (int)probs[i].n
                                 : L.ip[i].z.C;
       for (int r = 0; r < cnt; ++r) items.push_back(make_int4(i, ph, r, 0));
-      runs.back().count += cnt;
+      runs->back().count += cnt;
     }
   }
   e = hipMemcpyAsync(base + L.off_inst, inst.data(), sizeof(BatchInst) * count,
@@ -184,8 +170,51 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
     e = hipMemcpyAsync(base + L.off_items, items.data(), 16 * items.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);     // host lists must outlive the copies
   if (e != hipSuccess) return status_from_hip(e, "batch upload");
+  return HMV_OK;
+}
+
+int batch_check(const hmv_problem* probs, int32_t count, bool allow3, void* ws, int64_t ws_bytes,
+                BatchLayout* L) {
+  if (!batch_layout(probs, count, allow3, L)) return HMV_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (!probs[i].h || !probs[i].x || !probs[i].y) return HMV_EINVAL;
+  if (!ws || ws_bytes < L->total) return HMV_ENOMEM;
+  return HMV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t hmv_batch_workspace_bytes(const hmv_problem* probs, int32_t count) {
+  BatchLayout L;
+  if (!batch_layout(probs, count, !kBatchPersistent, &L)) return HMV_EINVAL;
+  return L.total;
+}
+
+int64_t hmv_batch_single_workspace_bytes(const hmv_problem* probs, int32_t count) {
+  BatchLayout L;
+  if (!batch_layout(probs, count, false, &L)) return HMV_EINVAL;
+  return L.total;
+}
+
+int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t ws_bytes,
+                     void* stream) {
+  const bool allow3 = !kBatchPersistent;
+  BatchLayout L;
+  int rc = batch_check(probs, count, allow3, ws, ws_bytes, &L);
+  if (rc != HMV_OK) return rc;
+  clear_stale_error();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  std::vector<Run> runs;
+  int starts[4];
+  rc = batch_prepare(probs, count, L, base, s, &runs, starts);
+  if (rc != HMV_OK) return rc;
+  DevStatus* st = reinterpret_cast<DevStatus*>(base);
   const BatchInst* d_inst = reinterpret_cast<const BatchInst*>(base + L.off_inst);
   const int4* d_items = reinterpret_cast<const int4*>(base + L.off_items);
+  hipError_t e = hipSuccess;
   if (kBatchPersistent) {
     int dev = 0, cus = 0;
     e = hipGetDevice(&dev);
@@ -204,9 +233,27 @@ int hmv_batch_matvec(const hmv_problem* probs, int32_t count, void* ws, int64_t 
   return status_from_hip(e, "batch kernels");
 }
 
+int hmv_batch_matvec_single(const hmv_problem* probs, int32_t count, void* ws, int64_t ws_bytes,
+                            void* stream) {
+  BatchLayout L;
+  int rc = batch_check(probs, count, false, ws, ws_bytes, &L);
+  if (rc != HMV_OK) return rc;
+  clear_stale_error();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  std::vector<Run> runs;
+  int starts[4];
+  rc = batch_prepare(probs, count, L, base, s, &runs, starts);
+  if (rc != HMV_OK) return rc;
+  hipError_t e = launch_batch_coop(reinterpret_cast<const BatchInst*>(base + L.off_inst),
+                                   reinterpret_cast<const int4*>(base + L.off_items), starts,
+                                   L.nitems, reinterpret_cast<DevStatus*>(base), nullptr, s);
+  return status_from_hip(e, "batch cooperative kernel");
+}
+
 int32_t hmv_batch_launches(const hmv_problem* probs, int32_t count) {
   BatchLayout L;
-  if (!batch_layout(probs, count, &L)) return HMV_EINVAL;
+  if (!batch_layout(probs, count, !kBatchPersistent, &L)) return HMV_EINVAL;
   std::vector<int> limb, index;
   for (int i = 0; i < count; ++i) {
     limb.push_back(L.ip[i].z.logM + (L.ip[i].z.z3 ? kBatchLog3 : 0));

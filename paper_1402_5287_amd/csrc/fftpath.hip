@@ -22,6 +22,8 @@
 // columns of the tile run on the same XCD, column order being remapped per
 // XCD, and hit in its L2).  TW = 2^lt is a run-time choice per plan, picked
 // for the spectra of x and of y separately by the planner's timing runs.
+#include <hip/hip_cooperative_groups.h>
+
 #include <mutex>
 #include <vector>
 
@@ -1423,6 +1425,73 @@ hipError_t launch_batch_phase(int phase, int logn, const BatchInst* inst, const 
   else
     hipLaunchKernelGGL(k_batch_rows_inv, dim3(nitems), dim3(T), lds, s, inst, items, nitems, st);
   return hipGetLastError();
+}
+
+// Single cooperative launch of a whole batch: every work-group stays
+// resident (the launch is refused otherwise), takes the items of pass 0 in a
+// grid-stride loop, waits at a grid-wide barrier, then takes those of pass
+// 1, and so on.  The passes' items are independent within a pass and the
+// barriers order the passes, so no work-group waits on another's progress
+// except at the three barriers, which every work-group reaches.  One
+// work-group shape serves every item: 256 threads, power-of-two limb
+// transforms (the pass bodies of the persistent form).
+__global__ void __launch_bounds__(256) k_batch_coop(const BatchInst* __restrict__ inst,
+                                                    const int4* __restrict__ items, int4 starts,
+                                                    int nitems, DevStatus* st) {
+  extern __shared__ double2 buf[];
+  __shared__ uint64_t wd[kMaxWords];
+  __shared__ uint32_t red[32];
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  for (int ph = 0; ph < 4; ++ph) {
+    const int lo = ph == 0 ? starts.x : ph == 1 ? starts.y : ph == 2 ? starts.z : starts.w;
+    const int hi = ph == 0 ? starts.y : ph == 1 ? starts.z : ph == 2 ? starts.w : nitems;
+    for (int it = lo + (int)blockIdx.x; it < hi; it += (int)gridDim.x) {
+      const int4 d = items[it];
+      const BatchInst I = inst[d.x];
+      const int rows_h = 2 * I.n - 1;
+      if (ph == 0) {
+        if (d.z < rows_h)
+          b_row_fwd(I.h, I.W, I.P, I.w, I.L, I.gather, I.logM, I.H1, rows_h, d.z, buf, wd, red,
+                    st);
+        else
+          b_row_fwd(I.x, I.W, I.P, I.w, I.L, 0, I.logM, I.X1, I.n, d.z - rows_h, buf, wd, red,
+                    st);
+      } else if (ph == 1) {
+        b_col_plan(I.H1, rows_h, I.logNt, I.scale, I.Hh, d.z, buf);
+      } else if (ph == 2) {
+        b_col_pass(I.X1, I.Hh, I.n, I.logNt, I.Y1, d.z, buf);
+      } else {
+        b_row_inv(I.Y1, I.n, I.logM, I.L, I.w, I.P, I.W, I.reverse, I.y, d.z, buf, red, st);
+      }
+      __syncthreads();
+    }
+    if (ph < 3) grid.sync();
+  }
+}
+
+hipError_t launch_batch_coop(const BatchInst* inst, const int4* items, const int* starts,
+                             int nitems, DevStatus* st, int* grid_used, hipStream_t s) {
+  hipError_t e = fft_tables_init();
+  if (e != hipSuccess) return e;
+  const size_t lds = kBatchDynLds;
+  e = set_lds((const void*)k_batch_coop, lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, cus = 0, per_cu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_coop,
+                                                     kBatchThreads, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  const int grid = per_cu * cus;
+  if (grid_used) *grid_used = grid;
+  int4 st4 = make_int4(starts[0], starts[1], starts[2], starts[3]);
+  void* args[] = {(void*)&inst, (void*)&items, (void*)&st4, (void*)&nitems, (void*)&st};
+  e = hipLaunchCooperativeKernel((const void*)k_batch_coop, dim3(grid), dim3(kBatchThreads), args,
+                                 lds, s);
+  return e;
 }
 
 __global__ void k_zero_ints(int* p, int count) {

@@ -12,7 +12,7 @@ struct DevStatus;
 constexpr int kMaxWords = 648;      // W for P up to 40960 is 641
 constexpr int kSchoolMaxK = 16;      // outputs per thread of the schoolbook kernel, at most
 constexpr int kSchoolThreads = 512;  // work-group size of the schoolbook kernel
-constexpr int kBatchThreads = 256;   // work-group size of the single-launch batch kernel
+constexpr int kBatchThreads = 256;   // work-group size of the single-launch batch kernels
 
 // status block
 hipError_t launch_clear_status(DevStatus* st, hipStream_t s);
@@ -110,6 +110,11 @@ struct BatchInst {
 };
 
 constexpr size_t kBatchDynLds = 72 * 1024;   // dynamic LDS of the batch kernel
+// the whole batch in one cooperative launch (power-of-two limb transforms);
+// starts[p] = first item of pass p (items are pass-major); grid_used gets the
+// number of work-groups
+hipError_t launch_batch_coop(const BatchInst* inst, const int4* items, const int* starts,
+                             int nitems, DevStatus* st, int* grid_used, hipStream_t s);
 hipError_t launch_batch(const BatchInst* inst, const int4* items, int nitems, int* head, int* ctr,
                         int nctr, int grid, int spin_limit, DevStatus* st, hipStream_t s);
 // one pass (0 forward rows, 1 plan columns, 2 matvec columns, 3 inverse rows)

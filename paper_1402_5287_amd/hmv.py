@@ -68,6 +68,8 @@ SIGNATURES = {
     "hmv_debug_batch_spin_limit": (_c_int, [_c_i32]),
     "hmv_batch_workspace_bytes": (_c_i64, [_vp, _c_i32]),
     "hmv_batch_matvec": (_c_int, [_vp, _c_i32, _vp, _c_i64, _vp]),
+    "hmv_batch_matvec_single": (_c_int, [_vp, _c_i32, _vp, _c_i64, _vp]),
+    "hmv_batch_single_workspace_bytes": (_c_i64, [_vp, _c_i32]),
     "hmv_server_create": (_c_int, [ctypes.POINTER(_vp), _vp, _c_i64, _c_i32]),
     "hmv_server_add_plan": (_c_int, [_vp, _vp, ctypes.POINTER(_c_i32)]),
     "hmv_server_submit": (_c_int, [_vp, _c_i32, _c_i64, _vp, _vp, _vp, ctypes.POINTER(_c_i64)]),
@@ -411,6 +413,14 @@ def batch_workspace_bytes(problems) -> int:
     return int(b)
 
 
+def batch_single_workspace_bytes(problems) -> int:
+    b = lib().hmv_batch_single_workspace_bytes(ctypes.cast(problems, ctypes.c_void_p),
+                                               len(problems))
+    if b < 0:
+        raise HmvError(int(b), "hmv_batch_single_workspace_bytes")
+    return int(b)
+
+
 def batch_launches(problems) -> int:
     n = lib().hmv_batch_launches(ctypes.cast(problems, ctypes.c_void_p), len(problems))
     if n < 0:
@@ -425,6 +435,16 @@ def batch_matvec(problems, ws, stream=None, check=True) -> int:
                                 ws.numel(), _stream(stream))
     if check:
         _check(rc, "batch_matvec")
+    return rc
+
+
+def batch_matvec_single(problems, ws, stream=None, check=True) -> int:
+    """The same products in one cooperative launch (grid-wide barriers
+    between the passes)."""
+    rc = lib().hmv_batch_matvec_single(ctypes.cast(problems, ctypes.c_void_p), len(problems),
+                                       _ptr(ws), ws.numel(), _stream(stream))
+    if check:
+        _check(rc, "batch_matvec_single")
     return rc
 
 

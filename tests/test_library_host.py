@@ -122,3 +122,33 @@ def test_debug_switches_validate_and_restore():
     assert L.hmv_debug_force_tiles(8, 2) == 0
     assert L.hmv_debug_force_tiles(-1, -1) == 0
 
+
+def test_single_launch_batch_validation():
+    """The one-launch batch checks its arguments before any device work: bad
+    lists give HMV_EINVAL, a missing or short workspace HMV_ENOMEM (so the
+    256-instance mix has a power-of-two layout, which needs more workspace
+    than the per-pass driver's)."""
+    import seeded_inputs as si
+    hmv, L = _lib()
+    fake = 1 << 20                                 # never dereferenced on these paths
+    mix = si.batch_instances(256)
+    arr = (hmv.Problem * len(mix))()
+    for k, (kind, n, P) in enumerate(mix):
+        arr[k] = hmv.Problem(kind, P, n, fake, fake, fake)
+    ptr = ctypes.cast(arr, ctypes.c_void_p)
+    ws = L.hmv_batch_single_workspace_bytes(ptr, len(mix))
+    assert ws > L.hmv_batch_workspace_bytes(ptr, len(mix)) > 0
+    assert L.hmv_batch_matvec_single(ptr, len(mix), None, 0, None) == hmv.ENOMEM
+    assert L.hmv_batch_matvec_single(ptr, len(mix), ctypes.c_void_p(fake), ws - 1,
+                                     None) == hmv.ENOMEM
+    assert L.hmv_batch_matvec(ptr, len(mix), None, 0, None) == hmv.ENOMEM
+    assert L.hmv_batch_matvec_single(None, 3, None, 0, None) == hmv.EINVAL
+    assert L.hmv_batch_matvec_single(ptr, 0, None, 0, None) == hmv.EINVAL
+    bad = (hmv.Problem * 2)()
+    bad[0] = hmv.Problem(0, 64, 4, fake, fake, fake)
+    bad[1] = hmv.Problem(0, 64, 4, fake, 0, fake)           # null x
+    assert L.hmv_batch_matvec_single(ctypes.cast(bad, ctypes.c_void_p), 2, None, 0,
+                                     None) == hmv.EINVAL
+    bad[1] = hmv.Problem(0, 64, 4096, fake, fake, fake)     # n above the batch limit
+    assert L.hmv_batch_matvec_single(ctypes.cast(bad, ctypes.c_void_p), 2, None, 0,
+                                     None) == hmv.EINVAL
