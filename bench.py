@@ -144,6 +144,10 @@ def main():
                     help="comma-separated offered loads, as fractions of saturated throughput")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--serving-pool-gb", type=float, default=4.5)
+    ap.add_argument("--serving-max-large", type=int, default=0,
+                    help="large requests in flight at most (0: the server's default policy)")
+    ap.add_argument("--serving-large-mb", type=float, default=0.0,
+                    help="workspace above which a request is large (with --serving-max-large)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run a plain device copy of BYTES bytes (5 times), the reference "
                          "for scaling hardware byte counters")
@@ -682,6 +686,8 @@ def section_serving(dev, procs, args, pool_vectors=4):
         server = hmv.Server(pool_bytes, slots=args.serving_slots, device=dev)
         for p in plans:
             server.add_plan(p)
+        if args.serving_max_large > 0:
+            server.set_policy(int(args.serving_large_mb * 2**20), args.serving_max_large)
         wall, lats, recs = serving.run(server, sessions, time_limit=300.0)
         torch.cuda.synchronize()
         st = server.stats()
@@ -701,6 +707,8 @@ def section_serving(dev, procs, args, pool_vectors=4):
                          "workspace_mb": round(b / 2**20, 1)}
                         for (n, P), i, b in zip(mats, info, ws_need)],
            "slots": args.serving_slots, "pool_gb": args.serving_pool_gb,
+           "policy": {"large_mb": round(st["large_bytes"] / 2**20, 1),
+                      "max_large": st["max_large"]},
            "saturated_matvecs_per_s": round(sat_rate, 1), "loads": []}
     for li, load in enumerate(float(v) for v in args.serving_loads.split(",")):
         desc = si.serving_sessions(args.serving_sessions, len(mats), seed=li)
@@ -730,6 +738,7 @@ def section_serving(dev, procs, args, pool_vectors=4):
                                  "p99_ms": round(1e3 * serving.percentile(v, 0.99), 3),
                                  "count": len(v)} for n, v in sorted(by_n.items())},
                "max_in_flight": st["max_in_flight"],
+               "max_large_in_flight": st["max_large_in_flight"],
                "pool_peak_mb": round(st["pool_peak"] / 2**20, 1),
                "last_results_equal_alone": same}
         log(f"serving load {load}: {ent}")

@@ -319,10 +319,19 @@ typedef struct hmv_server hmv_server;
 typedef struct {
   int64_t in_flight, waiting, admitted, completed, max_in_flight;
   int64_t pool_used, pool_peak, pool_bytes;
+  int64_t large_in_flight, max_large_in_flight;   /* requests above large_bytes  */
+  int64_t large_bytes, max_large;                 /* the admission policy        */
 } hmv_server_stats_t;
 
 int hmv_server_create(hmv_server** out, void* pool, int64_t pool_bytes, int32_t max_slots);
 int hmv_server_add_plan(hmv_server* server, const hmv_plan* plan, int32_t* matrix_id);
+/* Size-aware admission: a request whose workspace is above large_bytes is
+ * large, and at most max_large (1 .. max_slots) large requests are in flight;
+ * a large request held back by that cap lets younger, smaller requests
+ * start.  Defaults: pool_bytes / 8 and max(1, max_slots / 4).  Takes effect
+ * at the next admission; HMV_EINVAL for large_bytes < 0 or max_large out of
+ * range.                                                                   */
+int hmv_server_set_policy(hmv_server* server, int64_t large_bytes, int32_t max_large);
 /* hmv_server_submit orders the request after all work enqueued on
  * `stream` (a hipStream_t, NULL = the null stream) before the call, as the
  * other entry points do: the server records an event there and the

@@ -9,7 +9,12 @@
 // still running.  Requests of one session run in submission order.
 // Admission is oldest-first with a reservation: while the oldest waiting
 // request cannot get memory, younger requests are admitted only if they
-// leave enough free memory for it (no starvation of large matrices).
+// leave enough free memory for it (no starvation of large matrices).  It is
+// also size-aware: a request whose workspace exceeds large_bytes is large,
+// and at most max_large of those run at once; a large request that finds
+// the cap reached is passed over (smaller ones behind it may start), so
+// small requests keep finding slots and do not queue behind the device
+// time of many large products.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -92,6 +97,7 @@ struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
+  bool large = false;
   Request req;
 };
 
@@ -108,6 +114,9 @@ struct hmv_server {
   int64_t next_id = 1;
   int64_t completed = 0, admitted = 0;
   int max_inflight = 0;
+  int64_t large_bytes = 0;        // workspace above which a request is large
+  int max_large = 1;              // large requests in flight at most
+  int large_inflight = 0, max_large_seen = 0;
 };
 
 namespace {
@@ -129,6 +138,11 @@ int admit(hmv_server* S) {
       }
     if (slot < 0) break;
     const int64_t need = align_up(r.ws_bytes);
+    const bool large = need > S->large_bytes;
+    if (large && S->large_inflight >= S->max_large) {
+      ++it;
+      continue;
+    }
     if (blocked && S->alloc.largest() - need < reserve) {
       ++it;
       continue;
@@ -154,6 +168,11 @@ int admit(hmv_server* S) {
       return rc;
     }
     sl.busy = true;
+    sl.large = large;
+    if (large) {
+      ++S->large_inflight;
+      S->max_large_seen = std::max(S->max_large_seen, S->large_inflight);
+    }
     sl.req = r;
     S->busy_sessions.insert(r.session);
     ++S->admitted;
@@ -177,6 +196,8 @@ int hmv_server_create(hmv_server** out, void* pool, int64_t pool_bytes, int32_t 
   S->pool = static_cast<char*>(pool);
   S->alloc.init(pool_bytes);
   S->slots.resize(max_slots);
+  S->large_bytes = S->alloc.size / 8;
+  S->max_large = std::max(1, max_slots / 4);
   for (auto& sl : S->slots) {
     if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
@@ -244,7 +265,9 @@ int hmv_server_poll(hmv_server* S, int64_t* done_ids, int32_t* done_status, int3
     S->alloc.release(sl.req.ws_off, align_up(sl.req.ws_bytes));
     S->spare_events.push_back(sl.req.ready);   // its wait has been consumed
     S->busy_sessions.erase(sl.req.session);
+    if (sl.large) --S->large_inflight;
     sl.busy = false;
+    sl.large = false;
     ++S->completed;
   }
   (void)hipGetLastError();
@@ -262,6 +285,18 @@ int hmv_server_stats(const hmv_server* S, hmv_server_stats_t* st) {
   st->pool_used = S->alloc.used;
   st->pool_peak = S->alloc.peak;
   st->pool_bytes = S->alloc.size;
+  st->large_in_flight = S->large_inflight;
+  st->max_large_in_flight = S->max_large_seen;
+  st->large_bytes = S->large_bytes;
+  st->max_large = S->max_large;
+  return HMV_OK;
+}
+
+int hmv_server_set_policy(hmv_server* S, int64_t large_bytes, int32_t max_large) {
+  if (!S || large_bytes < 0 || max_large < 1 || max_large > (int32_t)S->slots.size())
+    return HMV_EINVAL;
+  S->large_bytes = large_bytes;
+  S->max_large = max_large;
   return HMV_OK;
 }
 

@@ -76,6 +76,7 @@ SIGNATURES = {
     "hmv_server_poll": (_c_int, [_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i32), _c_i32,
                                  ctypes.POINTER(_c_i32)]),
     "hmv_server_stats": (_c_int, [_vp, _vp]),
+    "hmv_server_set_policy": (_c_int, [_vp, _c_i64, _c_i32]),
     "hmv_server_destroy": (_c_int, [_vp]),
 }
 
@@ -84,7 +85,9 @@ class ServerStats(ctypes.Structure):
     """Mirror of hmv_server_stats_t."""
     _fields_ = [(f, ctypes.c_int64) for f in ("in_flight", "waiting", "admitted", "completed",
                                               "max_in_flight", "pool_used", "pool_peak",
-                                              "pool_bytes")]
+                                              "pool_bytes", "large_in_flight",
+                                              "max_large_in_flight", "large_bytes",
+                                              "max_large")]
 
 
 class Problem(ctypes.Structure):
@@ -470,6 +473,12 @@ class Server:
         _check(lib().hmv_server_add_plan(self.handle, plan.handle, ctypes.byref(mid)), "add_plan")
         self.plans.append(plan)
         return int(mid.value)
+
+    def set_policy(self, large_bytes: int, max_large: int) -> None:
+        """Requests with workspace above large_bytes are large; at most
+        max_large of them run at once."""
+        _check(lib().hmv_server_set_policy(self.handle, int(large_bytes), int(max_large)),
+               "server_set_policy")
 
     def submit(self, matrix_id: int, session: int, x, y, stream=None) -> int:
         """Queue one matvec; it runs after the work already queued on `stream`

@@ -109,3 +109,48 @@ def test_submit_waits_for_the_producer_stream():
         assert torch.count_nonzero(y).item() > 0
     server.close()
     plan.close()
+
+
+def test_size_aware_admission():
+    """With at most one large request in flight, a large request held back by
+    the cap lets the small ones behind it start; every result still equals
+    the product alone."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    big = hmv.Plan("hankel", hmv.to_device(si.uniform(2 * 2000 - 1, 3322, (94, 0))), 2000, 3322)
+    small = hmv.Plan("toeplitz", hmv.to_device(si.uniform(2 * 64 - 1, 3322, (94, 1))), 64, 3322)
+    server = hmv.Server(pool_bytes=4 * big.mv_ws_bytes + 4 * small.mv_ws_bytes, slots=4)
+    mb, ms = server.add_plan(big), server.add_plan(small)
+    with pytest.raises(hmv.HmvError):
+        server.set_policy(small.mv_ws_bytes * 2, 5)         # more than the slots
+    with pytest.raises(hmv.HmvError):
+        server.set_policy(-1, 1)
+    server.set_policy(small.mv_ws_bytes * 2, 1)
+    jobs = [(mb, 2000, 3322, 0), (mb, 2000, 3322, 1), (mb, 2000, 3322, 2),
+            (ms, 64, 3322, 3), (ms, 64, 3322, 4), (ms, 64, 3322, 5)]
+    xs, ys = [], []
+    for mid, n, P, sid in jobs:
+        xs.append(hmv.to_device(si.uniform(n, P, (95, sid))))
+        ys.append(torch.zeros((n, hmv.words(P)), dtype=torch.int64, device="cuda"))
+    announce("serving size-aware admission")
+    for (mid, n, P, sid), x, y in zip(jobs, xs, ys):
+        server.submit(mid, sid, x, y)
+    st = server.stats()
+    # one large and the three small requests run; two large ones wait
+    assert st["in_flight"] == 4 and st["waiting"] == 2 and st["large_in_flight"] == 1
+    done = []
+    t0 = time.time()
+    while len(done) < len(jobs):
+        assert time.time() - t0 < 60
+        done += server.poll()
+        time.sleep(1e-4)
+    assert all(status == 0 for _, status in done)
+    st = server.stats()
+    assert st["max_large_in_flight"] == 1 and st["completed"] == len(jobs)
+    for (mid, n, P, sid), x, y in zip(jobs, xs, ys):
+        plan = big if mid == mb else small
+        alone = torch.zeros_like(y)
+        plan.matvec(x, alone, ws=plan.new_workspace())
+        torch.cuda.synchronize()
+        assert torch.equal(alone, y), sid
+    server.close()
