@@ -315,21 +315,25 @@ __host__ __device__ inline int carry_lds_bytes(int T) { return 8 * T + 64; }
 // strided LDS accesses spread over the banks, and E w >= 60).
 //  1. Each chunk is normalised on its own: limbs in [0, 2^w) (floor
 //     division), leaving a carry C_t with |C_t| < 2^55 for the next chunk.
-//  2. Adding C_{t-1} to chunk t may carry one more unit out of it, in
-//     either direction; what leaves chunk t for an extra incoming
-//     kappa in {-1, 0, 1} depends only on its low limbs (which absorb
-//     C_{t-1}) and on whether its other limbs are all 0 or all 2^w - 1.
-//     These maps are composed by a block scan, which gives every chunk its
-//     kappa.
-//  3. Each chunk adds C_{t-1} + kappa; the top chunk keeps what leaves the
-//     limbs plus its own C (S = sum limbs 2^(w e) + top 2^(w NC)).
+//  2. Chunk t adds C_{t-1}: limbs R' = (R + C_{t-1}) mod 2^(w E) and an
+//     outgoing carry c in {-1, 0, 1} (|C_{t-1}| < 2^(w E)).  One more unit
+//     kappa in {-1, 0, 1} arriving from below changes what leaves the chunk
+//     only if R' is 0 (kappa = -1 borrows through it) or 2^(w E) - 1
+//     (kappa = 1 carries through it), so the map kappa -> outgoing carry is
+//     (c - [R' = 0], c, c + [R' all ones]).  A block scan composes these
+//     maps, which gives every chunk its kappa.
+//  3. A chunk with kappa != 0 adds it to R' (the unit ripples through the
+//     low limbs that are all ones, or all zeros for a borrow); the top chunk
+//     keeps what leaves the limbs plus its own C (S = sum limbs 2^(w e) +
+//     top 2^(w NC)).
 // Then the round bit (P-1), the sticky OR below it and bit P decide the
 // round-half-even increment of floor(S / 2^P), whose words are cut from the
 // limbs; the increment ripples through the lowest all-ones words.
 // P = 0 asks for S itself, unrounded: its W low words (the caller sizes W
 // for the whole sum; the floating-point interface keeps exact sums).
 // Limbs a thread keeps in registers during the carry passes; a longer chunk
-// (only for very large P at small widths) runs the same passes from LDS.
+// (only for very large P at small widths) or a width outside 8..24 runs the
+// passes from LDS.
 constexpr int kCarryRegs = 32;
 
 // chunk length of carry_round_pack for NC coefficients over T threads
@@ -340,106 +344,182 @@ __host__ __device__ inline int carry_chunk(int NC, int w, int T) {
   return E | 1;
 }
 
-// REGS: limbs per thread held in registers (the unrolled length of the
-// chunk loops); carry_round_pack_fit picks the smallest of 9, 13, 17, 25 and
-// 32 that holds a chunk (13 and 25 are the chunks of the 4096-point inverse
-// pass at 512 and 256 threads).
+// Steps 1-3 with the chunk in registers, REGS >= E limbs per thread, for
+// 8 <= w <= 24.  The limbs are kept as uint32.  From step 2 on the carry
+// shrinks by w bits per limb: after four limbs it fits 32 bits (|C| <
+// 2^55), and the rest of the chain runs in 32-bit arithmetic.  Returns the
+// sticky flag of this thread's limbs; the top value goes to
+// cs[blockDim.x].
 template <int REGS>
-__device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, int P, int W, int64_t* cs,
-                                        uint64_t* __restrict__ y, uint32_t* red) {
+__device__ __forceinline__ int carry_limbs_regs(int64_t* coef, int NC, int w, int E, int ep,
+                                                int rp, int64_t* cs, uint32_t* red) {
   const int T = blockDim.x, t = threadIdx.x;
   const int64_t mask = (int64_t(1) << w) - 1;
-  const int E = carry_chunk(NC, w, T);
+  const uint32_t mask32 = (uint32_t)mask;
   const int nch = (NC + E - 1) / E;
   const int e0 = t * E, e1 = min(NC, e0 + E);
   const bool own = t < nch;
   const int len = own ? e1 - e0 : 0;
-  const bool in_regs = E <= REGS;         // uniform
-  int64_t r[REGS];
-  // 1. chunk-local normalisation
+  uint32_t r[REGS];
+  // 1. chunk-local normalisation (in place in v, whose registers the limbs
+  //    then reuse)
   int64_t cown = 0;
-  if (in_regs) {
+  {
+    int64_t v[REGS];
+#pragma unroll
+    for (int j = 0; j < REGS; ++j) v[j] = coef[e0 + j < NC ? e0 + j : NC - 1];
 #pragma unroll
     for (int j = 0; j < REGS; ++j) {
-      const int e = e0 + j < NC ? e0 + j : NC - 1;
-      r[j] = coef[e];
-    }
-#pragma unroll
-    for (int j = 0; j < REGS; ++j) {
-      const int64_t c = r[j] + cown;
+      const int64_t c = v[j] + cown;
       const bool in = j < len;
-      r[j] = in ? (c & mask) : 0;
+      v[j] = in ? (c & mask) : 0;
       cown = in ? (c >> w) : cown;
     }
-  } else if (own) {
+#pragma unroll
+    for (int j = 0; j < REGS; ++j) r[j] = (uint32_t)v[j];
+  }
+  if (own) cs[t] = cown;
+  __syncthreads();
+  const int64_t cin = (own && t > 0) ? cs[t - 1] : 0;
+  // 2. add the incoming carry once; all-zero / all-ones flags of the result
+  int64_t c64 = cin;
+  int32_t c32 = 0;
+  bool allz = true, allo = true;
+#pragma unroll
+  for (int j = 0; j < REGS; ++j) {
+    const bool in = j < len;
+    uint32_t rn;
+    if (j < 4) {
+      const int64_t v = (int64_t)r[j] + c64;
+      rn = (uint32_t)(v & mask);
+      c64 = in ? (v >> w) : c64;
+      if (j == 3) c32 = (int32_t)c64;
+    } else {
+      const int32_t v = (int32_t)r[j] + c32;
+      rn = (uint32_t)v & mask32;
+      c32 = in ? (v >> w) : c32;
+    }
+    r[j] = in ? rn : r[j];
+    allz = allz && (!in || rn == 0u);
+    allo = allo && (!in || rn == mask32);
+  }
+  // the outgoing carry: in {-1, 0, 1} for every chunk but the top one, whose
+  // carry may be large when it is shorter than four limbs (then it is c64)
+  const int64_t cfin = len > 3 ? (int64_t)c32 : c64;
+  const int c0 = (int)cfin;
+  uint32_t g = kWordIdent;
+  if (own && t < nch - 1) {
+    const int cm = c0 - (allz ? 1 : 0), cp = c0 + (allo ? 1 : 0);
+    g = (uint32_t)(cm + 1) | ((uint32_t)(c0 + 1) << 2) | ((uint32_t)(cp + 1) << 4);
+  }
+  const uint32_t pre = block_exclusive_scan(g, kWordIdent, WordOp(), red);
+  const int kap = own && t > 0 ? (int)((pre >> 2) & 3u) - 1 : 0;   // the map applied to 0
+  // 3. the extra unit (rare: a whole chunk of zeros or of ones above it)
+  int64_t carry = cfin;
+  if (kap != 0) {
+    int k = kap;
+#pragma unroll
+    for (int j = 0; j < REGS; ++j) {
+      if (j < len) {
+        const int64_t v = (int64_t)r[j] + k;
+        r[j] = (uint32_t)(v & mask);
+        k = (int)(v >> w);
+      }
+    }
+    carry += k;
+  }
+  // sticky bit: any 1 below the round bit (none when ep < 0)
+  const uint32_t rpmask = (uint32_t)((int64_t(1) << rp) - 1);
+  int st = 0;
+#pragma unroll
+  for (int j = 0; j < REGS; ++j) {
+    const int e = e0 + j;
+    const uint32_t low = e < ep ? r[j] : (e == ep ? (r[j] & rpmask) : 0u);
+    if (j < len && low) st = 1;
+  }
+  if (own) {
+#pragma unroll
+    for (int j = 0; j < REGS; ++j)
+      if (j < len) coef[e0 + j] = (int64_t)r[j];
+  }
+  if (own && t == nch - 1) cs[T] = carry + cown;   // the top chunk's own C too
+  return st;
+}
+
+// Steps 1-3 from LDS: chunks longer than kCarryRegs limbs, and widths
+// outside 8..24 (64-bit arithmetic throughout).
+__device__ __forceinline__ int carry_limbs_lds(int64_t* coef, int NC, int w, int E, int ep, int rp,
+                                      int64_t* cs, uint32_t* red) {
+  const int T = blockDim.x, t = threadIdx.x;
+  const int64_t mask = (int64_t(1) << w) - 1;
+  const int nch = (NC + E - 1) / E;
+  const int e0 = t * E, e1 = min(NC, e0 + E);
+  const bool own = t < nch;
+  int64_t cown = 0;
+  if (own) {
     for (int e = e0; e < e1; ++e) {
       const int64_t c = coef[e] + cown;
       coef[e] = c & mask;
       cown = c >> w;
     }
+    cs[t] = cown;
   }
-  if (own) cs[t] = cown;
   __syncthreads();
   const int64_t cin = (own && t > 0) ? cs[t - 1] : 0;
-  // 2. carry map of the chunk: what leaves it when cin + kappa enters, for
-  //    kappa = -1, 0, 1 (three independent floor-division chains; each
-  //    result is -1, 0 or 1 because |cin| + 1 < 2^(w E)).  Identity for the
-  //    top chunk and idle threads.
+  int64_t c = cin;
+  bool allz = true, allo = true;
+  if (own) {
+    for (int e = e0; e < e1; ++e) {
+      const int64_t v = coef[e] + c;
+      coef[e] = v & mask;
+      c = v >> w;
+      allz = allz && coef[e] == 0;
+      allo = allo && coef[e] == mask;
+    }
+  }
+  const int c0 = (int)c;                           // in {-1, 0, 1} below the top chunk
   uint32_t g = kWordIdent;
   if (own && t < nch - 1) {
-    int64_t cm = cin - 1, c0 = cin, cp = cin + 1;
-    if (in_regs) {
-#pragma unroll
-      for (int j = 0; j < REGS; ++j) {
-        const bool in = j < len;
-        cm = in ? (r[j] + cm) >> w : cm;
-        c0 = in ? (r[j] + c0) >> w : c0;
-        cp = in ? (r[j] + cp) >> w : cp;
-      }
-    } else {
-      for (int e = e0; e < e1; ++e) {
-        cm = (coef[e] + cm) >> w;
-        c0 = (coef[e] + c0) >> w;
-        cp = (coef[e] + cp) >> w;
-      }
-    }
+    const int cm = c0 - (allz ? 1 : 0), cp = c0 + (allo ? 1 : 0);
     g = (uint32_t)(cm + 1) | ((uint32_t)(c0 + 1) << 2) | ((uint32_t)(cp + 1) << 4);
   }
   const uint32_t pre = block_exclusive_scan(g, kWordIdent, WordOp(), red);
-  const int kap = (int)((pre >> 2) & 3u) - 1;      // the map applied to kappa_0 = 0
-  // 3. incoming carry; sticky bit (any 1 below bit P-1) from the final limbs
-  //    (no rounding with P = 0: ep = -1 leaves no limb below the round bit)
-  const bool exact = P <= 0;
-  const int ep = exact ? -1 : (P - 1) / w, rp = exact ? 0 : (P - 1) - ep * w;
+  const int kap = own && t > 0 ? (int)((pre >> 2) & 3u) - 1 : 0;
+  int64_t carry = c;
   const int64_t rpmask = (int64_t(1) << rp) - 1;
-  int64_t carry = cin + kap;
   int st = 0;
-  if (in_regs) {
-#pragma unroll
-    for (int j = 0; j < REGS; ++j) {
-      const int64_t c = r[j] + carry;
-      const bool in = j < len;
-      r[j] = c & mask;
-      carry = in ? (c >> w) : carry;
-      const int e = e0 + j;
-      const int64_t low = e < ep ? r[j] : (e == ep ? (r[j] & rpmask) : 0);
-      if (in && low) st = 1;
-    }
-    if (own) {
-#pragma unroll
-      for (int j = 0; j < REGS; ++j)
-        if (j < len) coef[e0 + j] = r[j];
-    }
-  } else if (own) {
+  if (own) {
+    int k = kap;
     for (int e = e0; e < e1; ++e) {
-      const int64_t c = coef[e] + carry;
-      coef[e] = c & mask;
-      carry = c >> w;
+      if (k != 0) {
+        const int64_t v = coef[e] + k;
+        coef[e] = v & mask;
+        k = (int)(v >> w);
+      }
       const int64_t low = e < ep ? coef[e] : (e == ep ? (coef[e] & rpmask) : 0);
       if (low) st = 1;
     }
+    carry += k;
+    if (t == nch - 1) cs[T] = carry + cown;
   }
-  if (own && t == nch - 1) cs[T] = carry + cown;   // the top chunk's own C too
+  return st;
+}
+
+// The carry, the rounding and the output words.
+template <int REGS>
+__device__ __forceinline__ void carry_round_pack(int64_t* coef, int NC, int w, int P, int W, int64_t* cs,
+                                        uint64_t* __restrict__ y, uint32_t* red) {
+  const int T = blockDim.x, t = threadIdx.x;
+  const int E = carry_chunk(NC, w, T);
+  // round bit P-1 sits in limb ep at bit rp (no rounding with P = 0: ep = -1
+  // leaves no limb below the round bit)
+  const bool exact = P <= 0;
+  const int ep = exact ? -1 : (P - 1) / w, rp = exact ? 0 : (P - 1) - ep * w;
+  int st;
+  // (one register form only: a second one inlined beside it made the
+  // compiler keep both sets of limbs live)
+  if (E > REGS || w < 8 || w > 24) st = carry_limbs_lds(coef, NC, w, E, ep, rp, cs, red);
+  else st = carry_limbs_regs<REGS>(coef, NC, w, E, ep, rp, cs, red);
   if (t == 0) red[31] = (uint32_t)W;               // first word that is not all ones
   const int sticky = __syncthreads_or(st);
   const int64_t top = cs[T];
