@@ -370,6 +370,11 @@ int hmv_debug_force_layout(int32_t z3, int32_t pack);
  * plans for the spectra of x and of y; -1 keeps the tuned choice.
  * Returns HMV_EINVAL for other values.                                     */
 int hmv_debug_force_tiles(int32_t x_tile, int32_t y_tile);
+/* tests only: form of the schoolbook (HMV_SCHOOLBOOK): 0 = binary64 limb
+ * sums on the vector units, 1 = int8 limb products on the matrix cores
+ * (HMV_EUNSUPPORTED where its LDS row does not fit), -1 = the matrix-core
+ * form wherever it applies (the default).  Both give the same words.      */
+int hmv_debug_force_school(int32_t form);
 /* tests only: spin limit of the dependency waits of the single-launch batch
  * driver (switched off in this build; kept for its test); 0 = default.     */
 int hmv_debug_batch_spin_limit(int32_t spins);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -99,8 +100,69 @@ bool school_layout(int kind, int64_t n, int32_t P, SchoolLayout* lay) {
   return true;
 }
 
+// MFMA form of the schoolbook: 8-bit digits; Lp limbs (a multiple of the
+// 256-limb tile), the index axis padded to n64; h's limb-major rows hold R2
+// >= n + n64 + 8 bytes (every shifted stage load stays inside, zeros past
+// 2n - 1).
+struct SchoolMfmaLayout {
+  int L, Lp, R2, n64;
+  int64_t bytes;
+  int64_t off_hd, off_ht, off_xd, off_xt;
+};
+
+bool school_mfma_layout(int64_t n, int32_t P, SchoolMfmaLayout* m) {
+  m->L = limbs_of(P, 8);
+  m->Lp = (m->L + 255) / 256 * 256;
+  m->n64 = (int)((n + 63) / 64 * 64);
+  m->R2 = (int)((n + m->n64 + 8 + 63) / 64 * 64);
+  if (school_mfma_lds_bytes(m->Lp) > (size_t)kSchoolMfmaMaxLds) return false;
+  if ((int64_t)m->n64 * 16384 >= (int64_t(1) << 31)) return false;   // int32 sums stay exact
+  Carver c{nullptr, 0, INT64_MAX, true};
+  c.take(kStatusBytes);
+  m->off_hd = align_up(c.off);
+  c.take((2 * n - 1) * (int64_t)m->Lp);
+  m->off_ht = align_up(c.off);
+  c.take((int64_t)m->Lp * m->R2);
+  m->off_xd = align_up(c.off);
+  c.take(n * (int64_t)m->Lp);
+  m->off_xt = align_up(c.off);
+  c.take((int64_t)m->Lp * m->n64);
+  m->bytes = c.off;
+  return true;
+}
+
+int g_school_form = -1;   // -1: the MFMA form where it applies; 0: binary64 VALU; 1: MFMA
+
+int school_mfma_oneshot(int kind, const uint64_t* h, const uint64_t* x, uint64_t* y, int64_t n,
+                        int32_t P, const SchoolMfmaLayout& m, char* base, hipStream_t s) {
+  DevStatus* st = reinterpret_cast<DevStatus*>(base);
+  int8_t* hd = reinterpret_cast<int8_t*>(base + m.off_hd);
+  int8_t* ht = reinterpret_cast<int8_t*>(base + m.off_ht);
+  int8_t* xd = reinterpret_cast<int8_t*>(base + m.off_xd);
+  int8_t* xt = reinterpret_cast<int8_t*>(base + m.off_xt);
+  const int W = (int)words_of(P);
+  hipError_t e = launch_clear_status(st, s);
+  if (e != hipSuccess) return status_from_hip(e, "clear_status");
+  const int gather = (kind == HMV_CIRCULANT) ? (int)n : 0;
+  e = launch_split_digits_i8(h, W, P, m.L, m.Lp, (int)(2 * n - 1), gather, hd, st, s);
+  if (e == hipSuccess) e = launch_split_digits_i8(x, W, P, m.L, m.Lp, (int)n, 0, xd, st, s);
+  if (e == hipSuccess) e = launch_transpose_i8(hd, (int)(2 * n - 1), m.Lp, ht, m.R2, s);
+  if (e == hipSuccess) e = launch_transpose_i8(xd, (int)n, m.Lp, xt, m.n64, s);
+  if (e != hipSuccess) return status_from_hip(e, "school digits");
+  const int rev = (kind == HMV_HANKEL) ? 0 : 1;
+  e = launch_school_mfma(ht, xt, (int)n, m.L, m.Lp, m.R2, m.n64, P, W, rev, y, s);
+  return status_from_hip(e, "school mfma");
+}
+
 int school_oneshot(int kind, const uint64_t* h, const uint64_t* x, uint64_t* y, int64_t n,
                    int32_t P, void* ws, int64_t ws_bytes, hipStream_t s) {
+  SchoolMfmaLayout m;
+  const bool mfma_ok = school_mfma_layout(n, P, &m);
+  if (g_school_form != 0 && mfma_ok) {
+    if (!ws || ws_bytes < m.bytes) return HMV_ENOMEM;
+    return school_mfma_oneshot(kind, h, x, y, n, P, m, static_cast<char*>(ws), s);
+  }
+  if (g_school_form == 1) return HMV_EUNSUPPORTED;
   SchoolLayout lay;
   if (!school_layout(kind, n, P, &lay)) return HMV_EUNSUPPORTED;
   if (!ws || ws_bytes < lay.bytes) return HMV_ENOMEM;
@@ -166,12 +228,21 @@ const char* hmv_strerror(int code) {
 
 const char* hmv_last_error(void) { return g_last_error; }
 
+int hmv_debug_force_school(int32_t form) {
+  if (form < -1 || form > 1) return HMV_EINVAL;
+  g_school_form = form;
+  return HMV_OK;
+}
+
 int64_t hmv_oneshot_workspace_bytes(int kind, int64_t n, int32_t P, int algo) {
   if (!valid_kind(kind) || n < 1 || n > HMV_MAX_N || P < 1 || P > HMV_MAX_P) return HMV_EINVAL;
   if (algo == HMV_SCHOOLBOOK) {
+    // enough for either form
     SchoolLayout lay;
-    if (!school_layout(kind, n, P, &lay)) return HMV_EUNSUPPORTED;
-    return lay.bytes;
+    SchoolMfmaLayout m;
+    const bool v = school_layout(kind, n, P, &lay), q = school_mfma_layout(n, P, &m);
+    if (!v && !q) return HMV_EUNSUPPORTED;
+    return std::max(v ? lay.bytes : 0, q ? m.bytes : 0);
   }
   return oneshot_planned_bytes(kind, n, P, algo);
 }

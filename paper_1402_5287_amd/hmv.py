@@ -76,6 +76,7 @@ SIGNATURES = {
     "hmv_server_poll": (_c_int, [_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i32), _c_i32,
                                  ctypes.POINTER(_c_i32)]),
     "hmv_server_stats": (_c_int, [_vp, _vp]),
+    "hmv_debug_force_school": (_c_int, [_c_i32]),
     "hmv_server_set_policy": (_c_int, [_vp, _c_i64, _c_i32]),
     "hmv_server_destroy": (_c_int, [_vp]),
 }
@@ -398,6 +399,11 @@ def force_tiles(x_tile: int = -1, y_tile: int = -1) -> None:
 def force_width(w: int) -> None:
     """Tests only: restrict the binary64 limb width (0 = search)."""
     _check(lib().hmv_debug_force_width(w), "force_width")
+
+
+def force_school(form: int) -> None:
+    """Tests only: schoolbook form (0 vector FP64, 1 matrix-core int8, -1 default)."""
+    _check(lib().hmv_debug_force_school(form), "force_school")
 
 
 def batch_problems(items):

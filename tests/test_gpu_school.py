@@ -1,5 +1,6 @@
 """GPU schoolbook path (the plain sum of Section 2) against the oracle,
-bit-exact, through the C ABI."""
+bit-exact, through the C ABI; every test runs both forms (binary64 limb sums
+on the vector units, int8 limb products on the matrix cores)."""
 import numpy as np
 import pytest
 
@@ -8,6 +9,21 @@ from oracle import fixedpoint as fp, hankel
 from tests.gpu_util import announce, need_gpu, torch
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True, params=[0, 1], ids=["vector", "mfma"])
+def school_form(request):
+    from paper_1402_5287_amd import hmv
+    try:
+        hmv.lib()
+    except ImportError:
+        yield request.param
+        return
+    hmv.force_school(request.param)
+    try:
+        yield request.param
+    finally:
+        hmv.force_school(-1)
 
 
 def _run(kind, h, x, n, P, algo="schoolbook"):
@@ -102,3 +118,39 @@ def test_out_of_range_flag():
     announce("school range")
     _, rc, flags = _run("hankel", h, x, n, P)
     assert rc == -2 and (flags & 1)
+
+
+@pytest.mark.parametrize("n,P", [(3, 40960), (70, 33220), (300, 8), (257, 2000)])
+def test_paper_precisions(n, P, school_form):
+    """Large precisions (the MFMA form's LDS row at P = 40960 is its largest)
+    and index lengths across a 64-row stage boundary."""
+    need_gpu()
+    for kind in ("hankel", "circulant"):
+        hl = n if kind == "circulant" else 2 * n - 1
+        h = si.uniform(hl, P, (54, n, P))
+        x = si.uniform(n, P, (55, n, P))
+        announce("school precisions", school_form, kind, n, P)
+        y, rc, flags = _run(kind, h, x, n, P)
+        assert rc == 0 and flags == 0
+        assert np.array_equal(y, hankel.matvec_words(kind, h, x, P)), (kind, n, P)
+
+
+def test_forms_agree_at_n1024_p33220(school_form):
+    """Both forms give identical words on a paper-sized product (the oracle
+    is checked on sampled rows)."""
+    need_gpu()
+    from paper_1402_5287_amd import hmv
+    if school_form == 0:
+        pytest.skip("compared once, from the MFMA parametrisation")
+    n, P = 1024, 33220
+    h = si.uniform(2 * n - 1, P, (56,))
+    x = si.uniform(n, P, (57,))
+    announce("school forms agree", n, P)
+    y1, rc1, f1 = _run("toeplitz", h, x, n, P)
+    hmv.force_school(0)
+    y0, rc0, f0 = _run("toeplitz", h, x, n, P)
+    assert rc0 == rc1 == 0 and f0 == f1 == 0
+    assert np.array_equal(y0, y1)
+    rows = [0, 511, n - 1]
+    assert fp.decode(y1[rows]) == hankel.matvec_rows("toeplitz", fp.decode(h), fp.decode(x), P,
+                                                     rows, processes=3)
