@@ -102,8 +102,8 @@ bool school_layout(int kind, int64_t n, int32_t P, SchoolLayout* lay) {
 
 // MFMA form of the schoolbook: 8-bit digits; Lp limbs (a multiple of the
 // 256-limb tile), the index axis padded to n64; h's limb-major rows hold R2
-// >= n + n64 + 8 bytes (every shifted stage load stays inside, zeros past
-// 2n - 1).
+// >= n + n64 + 8 bytes (every stage load stays inside, zeros past 2n - 1),
+// in 16 copies, copy s shifted by s rows.
 struct SchoolMfmaLayout {
   int L, Lp, R2, n64;
   int64_t bytes;
@@ -122,7 +122,7 @@ bool school_mfma_layout(int64_t n, int32_t P, SchoolMfmaLayout* m) {
   m->off_hd = align_up(c.off);
   c.take((2 * n - 1) * (int64_t)m->Lp);
   m->off_ht = align_up(c.off);
-  c.take((int64_t)m->Lp * m->R2);
+  c.take(16 * (int64_t)m->Lp * m->R2);
   m->off_xd = align_up(c.off);
   c.take(n * (int64_t)m->Lp);
   m->off_xt = align_up(c.off);
@@ -146,7 +146,9 @@ int school_mfma_oneshot(int kind, const uint64_t* h, const uint64_t* x, uint64_t
   const int gather = (kind == HMV_CIRCULANT) ? (int)n : 0;
   e = launch_split_digits_i8(h, W, P, m.L, m.Lp, (int)(2 * n - 1), gather, hd, st, s);
   if (e == hipSuccess) e = launch_split_digits_i8(x, W, P, m.L, m.Lp, (int)n, 0, xd, st, s);
-  if (e == hipSuccess) e = launch_transpose_i8(hd, (int)(2 * n - 1), m.Lp, ht, m.R2, s);
+  for (int sft = 0; sft < 16 && e == hipSuccess; ++sft)
+    e = launch_transpose_i8(hd + (int64_t)sft * m.Lp, (int)(2 * n - 1) - sft, m.Lp,
+                            ht + (int64_t)sft * m.Lp * m.R2, m.R2, s);
   if (e == hipSuccess) e = launch_transpose_i8(xd, (int)n, m.Lp, xt, m.n64, s);
   if (e != hipSuccess) return status_from_hip(e, "school digits");
   const int rev = (kind == HMV_HANKEL) ? 0 : 1;

@@ -22,14 +22,15 @@ size_t school_lds_bytes(int L, int w, int P, int W);
 hipError_t launch_split_digits_f64(const uint64_t* in, int W, int P, int w, int L, int count,
                                    int gather_n, double* out, int ld, DevStatus* st,
                                    hipStream_t s);
-// schoolbook, MFMA form: 8-bit digits (int8), limb-major operands
+// schoolbook, MFMA form: 8-bit digits (int8), limb-major operands; Hs holds
+// 16 copies of h's, copy s shifted by s rows
 constexpr int kSchoolMfmaMaxLds = 160 * 1024;
 size_t school_mfma_lds_bytes(int Lp);
 hipError_t launch_split_digits_i8(const uint64_t* in, int W, int P, int L, int Lp, int count,
                                   int gather_n, int8_t* out, DevStatus* st, hipStream_t s);
 hipError_t launch_transpose_i8(const int8_t* src, int R, int Lp, int8_t* dst, int Rp,
                                hipStream_t s);
-hipError_t launch_school_mfma(const int8_t* Ht, const int8_t* Xt, int n, int L, int Lp, int R2,
+hipError_t launch_school_mfma(const int8_t* Hs, const int8_t* Xt, int n, int L, int Lp, int R2,
                               int n64, int P, int W, int out_reverse, uint64_t* y, hipStream_t s);
 hipError_t launch_school_rows(const double* hd, const double* xd, int n, int L, int ld, int w,
                               int P, int W, int out_reverse, uint64_t* y, hipStream_t s);

@@ -212,22 +212,32 @@ hipError_t launch_school_rows(const double* hd, const double* xd, int n, int L, 
 //     s_i[e]    = sum_{c + d = e} G_i[c][d]        (its anti-diagonal sums).
 // G_i's entries are below n 2^14 < 2^31 in magnitude, so int32 accumulation
 // is exact; the anti-diagonal sums are int64.  The digits are stored limb
-// major (Ht[c][r] = digit c of h row r, Xt[d][j]), so that both operands of
+// major (Hs[c][r] = digit c of h row r, Xt[d][j]), so that both operands of
 // v_mfma_i32_32x32x32_i8 read 16 consecutive bytes of the index axis per
 // lane; lanes 0-31 take the first 16 bytes of each 32-byte step and lanes
 // 32-63 the next 16, for A and B alike (the sum over k does not depend on
-// which lane carries which k).  A work-group (4 wavefronts) computes one row
-// i over tiles of 256 c x 128 d, each wavefront 128 x 64 (4 x 2 products of
-// 32 x 32), with the index axis staged through LDS 64 bytes at a time (two
-// buffers: the next stage's loads are in flight during the products).  Row
-// i's operand starts at index i, which need not be 8-byte aligned: each
-// stage loads 24 aligned bytes per 16 and shifts them by i mod 8 bytes.
-// After a tile, every lane adds its 128 products into s_i (int64 LDS
-// atomics); after all tiles the carry / round / pack step runs on s_i.
+// which lane carries which k).  A work-group (8 wavefronts, or 4 at the
+// largest precisions) computes one row i over tiles of 256 c x 256 d (256 x
+// 128), each wavefront 128 x 64 (4 x 2 products of 32 x 32), with the index
+// axis staged through LDS 64 bytes at a time (two LDS buffers; the loads of
+// a stage are issued two (four) stages ahead into a ring of register
+// sets).  Row i's operand starts at index i; h's digits
+// are kept in 16 copies, copy s shifted by s rows, so that row i reads copy
+// i mod 16 from a 16-byte aligned index and every load is one aligned
+// 16-byte access (about 16 x 36 MB at n = 4096, P = 33 220).
+// After the tiles that feed one band of anti-diagonals, every lane adds its
+// 128 sums into s_i (int64 LDS atomics); after all tiles the carry / round /
+// pack step runs on s_i.
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 typedef int v16i32 __attribute__((ext_vector_type(16)));
-constexpr int kSmTileC = 256, kSmTileD = 128, kSmStage = 64, kSmRow = 80;
-constexpr int kSmStageBytes = (kSmTileC + kSmTileD) * kSmRow;
+// Tiles: 256 c x 64 WD d per work-group of 2 x WD wavefronts, 128 c x 64 d
+// per wavefront (4 x 2 products of 32 x 32; with 4 x 4 the accumulators
+// alone fill the 256 accumulation registers and the kernel spills).  WD = 4
+// (8 wavefronts, two per SIMD) where the LDS holds its larger stages, else
+// 2.  A stage holds 64 index bytes of every operand row, rows 80 bytes apart
+// (16 bytes of padding spread the lanes' 16-byte reads over all banks).
+constexpr int kSmTileC = 256, kSmStage = 64, kSmRow = 80;
+__host__ __device__ constexpr int sm_stage_bytes(int WD) { return (kSmTileC + 64 * WD) * kSmRow; }
 
 // One work-group per number: range check, balanced 8-bit split into int8
 // digits, row-major out[r][0 .. Lp) with zeros from L on.
@@ -271,138 +281,169 @@ __global__ void __launch_bounds__(256) k_transpose_i8(const int8_t* __restrict__
       make_uint4(o[0], o[1], o[2], o[3]);
 }
 
-// Global loads of one stage (index bytes j0 .. j0 + 63 of every operand row).
-__device__ __forceinline__ void school_mfma_gload(const int8_t* __restrict__ Ht,
+// Global loads of one stage (index bytes j0 .. j0 + 63 of every operand
+// row) by the T = 128 WD threads: pieces t + T q, row piece / 4, 16 bytes
+// at (piece % 4) 16; PA = 1024 / T pieces of A, 2 of B per thread.  Ha is
+// the copy of h's digits shifted so that row i's index bytes start at the
+// 16-byte aligned ib.
+template <int WD>
+__device__ __forceinline__ void school_mfma_gload(const int8_t* __restrict__ Ha,
                                                   const int8_t* __restrict__ Xt, int R2, int n64,
                                                   int c0, int d0, int ib, int j0, int t,
-                                                  uint2 (&ra)[4][3], uint4 (&rb)[2]) {
+                                                  v4i32 (&ra)[8 / WD], v4i32 (&rb)[2]) {
+  constexpr int T = 128 * WD;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int piece = t + 256 * q, row = piece >> 2, off = (piece & 3) * 16;
-    const uint2* a = reinterpret_cast<const uint2*>(Ht + (int64_t)(c0 + row) * R2 + ib + j0 + off);
-    ra[q][0] = a[0];
-    ra[q][1] = a[1];
-    ra[q][2] = a[2];
+  for (int q = 0; q < 8 / WD; ++q) {
+    const int piece = t + T * q, row = piece >> 2, off = (piece & 3) * 16;
+    ra[q] = *reinterpret_cast<const v4i32*>(Ha + (int64_t)(c0 + row) * R2 + ib + j0 + off);
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int piece = t + 256 * q, row = piece >> 2, off = (piece & 3) * 16;
-    rb[q] = *reinterpret_cast<const uint4*>(Xt + (int64_t)(d0 + row) * n64 + j0 + off);
+    const int piece = t + T * q, row = piece >> 2, off = (piece & 3) * 16;
+    rb[q] = *reinterpret_cast<const v4i32*>(Xt + (int64_t)(d0 + row) * n64 + j0 + off);
   }
 }
 
-// The stage into LDS, the A pieces shifted by shq * 4 + shr bytes.
-__device__ __forceinline__ void school_mfma_lstore(unsigned char* buf, int shq, int shr, int t,
-                                                   const uint2 (&ra)[4][3],
-                                                   const uint4 (&rb)[2]) {
+// The stage into LDS.
+template <int WD>
+__device__ __forceinline__ void school_mfma_lstore(unsigned char* buf, int t,
+                                                   const v4i32 (&ra)[8 / WD],
+                                                   const v4i32 (&rb)[2]) {
+  constexpr int T = 128 * WD;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int piece = t + 256 * q, row = piece >> 2, off = (piece & 3) * 16;
-    const uint32_t d0 = ra[q][0].x, d1 = ra[q][0].y, d2 = ra[q][1].x, d3 = ra[q][1].y,
-                   d4 = ra[q][2].x, d5 = ra[q][2].y;
-    uint4 o;
-    if (shq) {
-      o.x = __builtin_amdgcn_alignbyte(d2, d1, shr);
-      o.y = __builtin_amdgcn_alignbyte(d3, d2, shr);
-      o.z = __builtin_amdgcn_alignbyte(d4, d3, shr);
-      o.w = __builtin_amdgcn_alignbyte(d5, d4, shr);
-    } else {
-      o.x = __builtin_amdgcn_alignbyte(d1, d0, shr);
-      o.y = __builtin_amdgcn_alignbyte(d2, d1, shr);
-      o.z = __builtin_amdgcn_alignbyte(d3, d2, shr);
-      o.w = __builtin_amdgcn_alignbyte(d4, d3, shr);
-    }
-    *reinterpret_cast<uint4*>(buf + row * kSmRow + off) = o;
+  for (int q = 0; q < 8 / WD; ++q) {
+    const int piece = t + T * q, row = piece >> 2, off = (piece & 3) * 16;
+    *reinterpret_cast<v4i32*>(buf + row * kSmRow + off) = ra[q];
   }
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int piece = t + 256 * q, row = piece >> 2, off = (piece & 3) * 16;
-    *reinterpret_cast<uint4*>(buf + (kSmTileC + row) * kSmRow + off) = rb[q];
+    const int piece = t + T * q, row = piece >> 2, off = (piece & 3) * 16;
+    *reinterpret_cast<v4i32*>(buf + (kSmTileC + row) * kSmRow + off) = rb[q];
   }
 }
 
-__global__ void __launch_bounds__(256) k_school_mfma(const int8_t* __restrict__ Ht,
-                                                      const int8_t* __restrict__ Xt, int n,
-                                                      int L, int Lp, int R2, int n64, int P,
-                                                      int W, int out_reverse,
-                                                      uint64_t* __restrict__ y) {
+// The products of one stage (two 32-byte steps) from the buffer at cur:
+// wavefront (wc, wd) covers c rows 128 wc .. + 127, d rows 64 wd .. + 63.
+__device__ __forceinline__ void school_mfma_stage(const unsigned char* cur, int wc, int wd,
+                                                  int lane, v16i32 (&acc)[4][2]) {
+#pragma unroll
+  for (int ks = 0; ks < kSmStage / 32; ++ks) {
+    const int kb = ks * 32 + (lane >> 5) * 16;
+    v4i32 a[4], b[2];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+      a[cb] = *reinterpret_cast<const v4i32*>(cur + (wc * 128 + cb * 32 + (lane & 31)) * kSmRow + kb);
+#pragma unroll
+    for (int db = 0; db < 2; ++db)
+      b[db] = *reinterpret_cast<const v4i32*>(
+          cur + (kSmTileC + wd * 64 + db * 32 + (lane & 31)) * kSmRow + kb);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+        acc[cb][db] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[cb], b[db], acc[cb][db], 0, 0, 0);
+  }
+}
+
+template <int WD, int NSET>
+__global__ void __launch_bounds__(128 * WD) k_school_mfma(const int8_t* __restrict__ Hs,
+                                                           const int8_t* __restrict__ Xt, int n,
+                                                           int L, int Lp, int R2, int n64, int P,
+                                                           int W, int out_reverse, int group,
+                                                           uint64_t* __restrict__ y) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ uint32_t red[32];
+  constexpr int SB = sm_stage_bytes(WD), TD = 64 * WD, RD = kSmTileC / TD;
   const int NCp = 2 * Lp - 1;
-  int64_t* S = reinterpret_cast<int64_t*>(smem + 2 * kSmStageBytes);
+  int64_t* S = reinterpret_cast<int64_t*>(smem + 2 * SB);
   int64_t* cs = S + NCp;
   const int i = blockIdx.x;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wc = wave & 1, wd = wave >> 1;
   for (int e = t; e < NCp; e += blockDim.x) S[e] = 0;
-  const int sh = i & 7, ib = i - sh, shq = sh >> 2, shr = sh & 3;
+  const int ib = i & ~15;                    // row i reads copy i % 16 from ib on
+  const int8_t* Ha = Hs + (int64_t)(i & 15) * Lp * R2;
   const int nst = n64 / kSmStage;
-  const int ntd = Lp / kSmTileD, ntiles = (Lp / kSmTileC) * ntd;
-  for (int tile = 0; tile < ntiles; ++tile) {
-    const int c0 = (tile / ntd) * kSmTileC, d0 = (tile % ntd) * kSmTileD;
-    v16i32 acc[4][2];
+  const int ntc = Lp / kSmTileC, ntd = Lp / TD;
+  // Tiles in order of c0 + d0 = TD g (g = RD ct + dt): the tiles of one g
+  // feed the same anti-diagonals, so with group != 0 (the host checked that
+  // the sum over a group stays below 2^31) their products accumulate in the
+  // registers and reach s_i once per g.
+  v16i32 acc[4][2];
+  const int ng = RD * (ntc - 1) + ntd;
+  for (int g = 0; g < ng; ++g) {
+    const int ct_lo = g - ntd + 1 > 0 ? (g - ntd + RD) / RD : 0;
+    const int ct_hi = min(ntc - 1, g / RD);
+    for (int ct = ct_lo; ct <= ct_hi; ++ct) {
+      const int dt = g - RD * ct;
+      const int c0 = ct * kSmTileC, d0 = dt * TD;
+      if (ct == ct_lo || !group) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+          for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
-    // staging: A pieces t + 256 q (row piece / 4, 16 bytes at (piece % 4) 16),
-    // 24 aligned bytes each for the shift; B pieces likewise, aligned.  The
-    // last stage loads and stores one stage more (a repeat of itself) into
-    // the buffer nobody reads any more, which keeps the loop free of
-    // conditions around the staging registers.
-    uint2 ra[4][3];
-    uint4 rb[2];
-    school_mfma_gload(Ht, Xt, R2, n64, c0, d0, ib, 0, t, ra, rb);
-    school_mfma_lstore(smem, shq, shr, t, ra, rb);
-    __syncthreads();
-    for (int stage = 0; stage < nst; ++stage) {
-      const unsigned char* cur = smem + (stage & 1) * kSmStageBytes;
-      school_mfma_gload(Ht, Xt, R2, n64, c0, d0, ib, min(stage + 1, nst - 1) * kSmStage, t, ra,
-                        rb);
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
+      }
+      // A ring of NSET register sets: set u % NSET holds stage u.  While
+      // stage s computes, the loads of stage s + NSET go to the set that
+      // held stage s (already in LDS), and stage s + 1, loaded NSET - 1
+      // stages earlier, goes to LDS after the products.  Past the last
+      // stage the loads repeat it and the stores go to the buffer nobody
+      // reads any more, which keeps the ring free of conditions.
+      v4i32 ra[NSET][8 / WD];
+      v4i32 rb[NSET][2];
 #pragma unroll
-      for (int ks = 0; ks < kSmStage / 32; ++ks) {
-        const int kb = ks * 32 + (lane >> 5) * 16;
-        v4i32 a[4], b[2];
+      for (int u = 0; u < NSET; ++u)
+        school_mfma_gload<WD>(Ha, Xt, R2, n64, c0, d0, ib, min(u, nst - 1) * kSmStage, t, ra[u],
+                              rb[u]);
+      school_mfma_lstore<WD>(smem, t, ra[0], rb[0]);
+      __syncthreads();
+      for (int s0 = 0; s0 < nst; s0 += NSET) {
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-          a[cb] = *reinterpret_cast<const v4i32*>(cur + (wc * 128 + cb * 32 + (lane & 31)) * kSmRow + kb);
-#pragma unroll
-        for (int db = 0; db < 2; ++db)
-          b[db] = *reinterpret_cast<const v4i32*>(
-              cur + (kSmTileC + wd * 64 + db * 32 + (lane & 31)) * kSmRow + kb);
+        for (int u = 0; u < NSET; ++u) {
+          const int stage = s0 + u;
+          if (stage < nst) {                                 // uniform
+            school_mfma_gload<WD>(Ha, Xt, R2, n64, c0, d0, ib,
+                                  min(stage + NSET, nst - 1) * kSmStage, t, ra[u], rb[u]);
+            school_mfma_stage(smem + (stage & 1) * SB, wc, wd, lane, acc);
+            school_mfma_lstore<WD>(smem + ((stage + 1) & 1) * SB, t, ra[(u + 1) % NSET],
+                                   rb[(u + 1) % NSET]);
+            __syncthreads();
+          }
+        }
+      }
+      if (ct == ct_hi || !group) {
+        // anti-diagonal sums: product (m, nn) of block (cb, db) is G[c][d]
+        // with c = c0 + 128 wc + 32 cb + m, d = d0 + 64 wd + 32 db + nn,
+        // m = 8 (r / 4) + 4 (lane / 32) + r % 4, nn = lane % 32: one base per
+        // lane and a constant offset per (cb, db, r), which the LDS atomic
+        // takes as an immediate
+        unsigned long long* Sb = reinterpret_cast<unsigned long long*>(
+            S + (c0 + 128 * wc + d0 + 64 * wd + 4 * (lane >> 5) + (lane & 31)));
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
           for (int db = 0; db < 2; ++db)
-            acc[cb][db] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[cb], b[db], acc[cb][db], 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+              atomicAdd(Sb + (32 * cb + 32 * db + 8 * (r >> 2) + (r & 3)),
+                        (unsigned long long)(int64_t)acc[cb][db][r]);
       }
-      school_mfma_lstore(smem + ((stage + 1) & 1) * kSmStageBytes, shq, shr, t, ra, rb);
-      __syncthreads();
     }
-    // anti-diagonal sums: product (m, nn) of block (cb, db) is G[c][d] with
-    // c = c0 + 128 wc + 32 cb + m, d = d0 + 64 wd + 32 db + nn
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-      for (int db = 0; db < 2; ++db)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), nn = lane & 31;
-          const int e = c0 + 128 * wc + 32 * cb + m + d0 + 64 * wd + 32 * db + nn;
-          atomicAdd(reinterpret_cast<unsigned long long*>(&S[e]),
-                    (unsigned long long)(int64_t)acc[cb][db][r]);
-        }
   }
   __syncthreads();
   const int row = out_reverse ? (n - 1 - i) : i;
   carry_round_pack_fit(S, 2 * L - 1, 8, P, W, cs, y + (int64_t)row * W, red);
 }
 
-size_t school_mfma_lds_bytes(int Lp) {
-  return (size_t)2 * kSmStageBytes + (size_t)(2 * Lp - 1) * 8 + (size_t)carry_lds_bytes(256) + 16;
+size_t school_mfma_lds_bytes_wd(int Lp, int WD) {
+  return (size_t)2 * sm_stage_bytes(WD) + (size_t)(2 * Lp - 1) * 8 +
+         (size_t)carry_lds_bytes(128 * WD) + 16;
 }
+
+// the smaller form (WD = 2) decides whether the MFMA path applies at all
+size_t school_mfma_lds_bytes(int Lp) { return school_mfma_lds_bytes_wd(Lp, 2); }
 
 hipError_t launch_split_digits_i8(const uint64_t* in, int W, int P, int L, int Lp, int count,
                                   int gather_n, int8_t* out, DevStatus* st, hipStream_t s) {
@@ -419,15 +460,23 @@ hipError_t launch_transpose_i8(const int8_t* src, int R, int Lp, int8_t* dst, in
   return hipGetLastError();
 }
 
-hipError_t launch_school_mfma(const int8_t* Ht, const int8_t* Xt, int n, int L, int Lp, int R2,
+hipError_t launch_school_mfma(const int8_t* Hs, const int8_t* Xt, int n, int L, int Lp, int R2,
                               int n64, int P, int W, int out_reverse, uint64_t* y,
                               hipStream_t s) {
-  const size_t lds = school_mfma_lds_bytes(Lp);
-  hipError_t e = hipFuncSetAttribute((const void*)k_school_mfma,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // a group's int32 sums stay exact: at most Lp/256 tiles of products below
+  // n 2^14 each
+  const int group = (int64_t)(Lp / kSmTileC) * n * 16384 < (int64_t(1) << 31) ? 1 : 0;
+  const bool wide = school_mfma_lds_bytes_wd(Lp, 4) <= (size_t)kSchoolMfmaMaxLds;
+  const size_t lds = school_mfma_lds_bytes_wd(Lp, wide ? 4 : 2);
+  const void* fn = wide ? (const void*)k_school_mfma<4, 2> : (const void*)k_school_mfma<2, 4>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_school_mfma, dim3(n), dim3(256), lds, s, Ht, Xt, n, L, Lp, R2, n64, P, W,
-                     out_reverse, y);
+  if (wide)
+    hipLaunchKernelGGL((k_school_mfma<4, 2>), dim3(n), dim3(512), lds, s, Hs, Xt, n, L, Lp, R2,
+                       n64, P, W, out_reverse, group, y);
+  else
+    hipLaunchKernelGGL((k_school_mfma<2, 4>), dim3(n), dim3(256), lds, s, Hs, Xt, n, L, Lp, R2,
+                       n64, P, W, out_reverse, group, y);
   return hipGetLastError();
 }
 
