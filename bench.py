@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-launch section")
     ap.add_argument("--no-serving", action="store_true", help="skip the scheduler section")
     ap.add_argument("--no-lanczos", action="store_true", help="skip the Lanczos section")
+    ap.add_argument("--no-float", action="store_true",
+                    help="skip the floating-point input section")
     ap.add_argument("--multi", default="2,4,8",
                     help="block sizes k of the multi-vector section (Y = A [x_1..x_k]); "
                          "empty = skip")
@@ -375,6 +377,7 @@ def main():
         else section_multi(plan, xs, ys, n, W, info, [int(k) for k in args.multi.split(",")],
                            K),
         "lanczos": None if args.no_lanczos else section_lanczos(dev),
+        "float_inputs": None if args.no_float else section_float(dev, h_dev, xs, n, P),
         "paths_n1024": None if args.no_paths else section_paths(dev),
         "batch": None if args.no_batch else section_batch(dev),
         "serving": None if args.no_serving else section_serving(dev, procs, args),
@@ -518,6 +521,70 @@ def section_lanczos(dev, steps=20):
                        "matvec_ms": round(mv, 4), "status": rc, "flags": flags}
         log(f"lanczos n={n}: {res[str(n)]}")
         plan.close()
+    return res
+
+
+def section_float(dev, h_words, xs, n, P, spread=64, steps=50):
+    """Floating-point inputs (hmv_fplan_*) at the headline shape: the session's
+    words as P-bit significands with seeded exponents spread over `spread`
+    bits; matvecs/s of the floating plan (fixed point at Q = P + spread bits
+    inside) next to the plain fixed-point plan at Q bits."""
+    import numpy as np
+    import torch
+
+    from paper_1402_5287_amd import hmv
+    rng = np.random.default_rng(7)
+    hl = h_words.shape[0]
+    he = torch.from_numpy(rng.integers(-spread, 1, size=hl).astype(np.int32)).to(dev)
+    xe = torch.from_numpy(rng.integers(-spread, 1, size=(xs.shape[0], n)).astype(np.int32)).to(dev)
+    t0 = time.time()
+    fplan = hmv.FPlan("hankel", h_words, he, n, P, spread)
+    torch.cuda.synchronize()
+    plan_ms = (time.time() - t0) * 1000
+    W = hmv.words(P)
+    ys = torch.zeros((n, W), dtype=torch.int64, device=dev)
+    ye = torch.zeros(n, dtype=torch.int32, device=dev)
+    for k in range(3):
+        fplan.matvec(xs[k], xe[k], ys, ye)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        fplan.matvec(xs[k % xs.shape[0]], xe[k % xs.shape[0]], ys, ye)
+    e1.record()
+    torch.cuda.synchronize()
+    fms = e0.elapsed_time(e1) / steps
+    rc, flags, _ = hmv.read_status(fplan.ws)
+    info = fplan.info()
+    fplan.close()
+    # the fixed-point plan at the same inner precision Q
+    Q = info["Q"]
+    WQ = hmv.words(Q)
+    hq = torch.zeros((hl, WQ), dtype=torch.int64, device=dev)
+    hq[:, :W] = h_words
+    hq[:, W:] = torch.where(h_words[:, W - 1:W] < 0, -1, 0)
+    xq = torch.zeros((n, WQ), dtype=torch.int64, device=dev)
+    xq[:, :W] = xs[0]
+    xq[:, W:] = torch.where(xs[0][:, W - 1:W] < 0, -1, 0)
+    qplan = hmv.Plan("hankel", hq, n, Q, algo="split_fft")
+    yq = torch.zeros_like(xq)
+    for _ in range(3):
+        qplan.matvec(xq, yq)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        qplan.matvec(xq, yq)
+    e1.record()
+    torch.cuda.synchronize()
+    qms = e0.elapsed_time(e1) / steps
+    qplan.close()
+    res = {"n": n, "P": P, "spread": spread, "Q": Q, "plan_ms": round(plan_ms, 1),
+           "matvec_ms": round(fms, 4), "matvecs_per_s": round(1000.0 / fms, 1),
+           "fixed_point_Q_matvec_ms": round(qms, 4), "status": rc, "flags": flags,
+           "w": info["w"], "Nz": info["Nz"]}
+    log(f"float inputs: {res}")
+    if rc != 0 or flags:
+        raise SystemExit("floating-point matvec reported a nonzero status")
     return res
 
 
