@@ -39,8 +39,16 @@ namespace {
 
 constexpr int kLzThreads = 256;
 constexpr int kLzLimbs = 2 * kMaxWords;              // 32-bit limbs of one number
-constexpr int kLzCols = (4 * kMaxWords + 2 + kLzThreads - 1) / kLzThreads;   // columns per thread
+// Column sums: the NC columns are cut into nbk = ceil(NC / kLzBlk) blocks of
+// kLzBlk; thread t owns block t and block t + ceil(nbk / 2).  A product's
+// column k has min(k + 1, NC - 1 - k) terms, rising then falling, so every
+// thread pairs a block of the rising half with the block of the falling half
+// whose length complements it, and all threads do about the same number of
+// limb products.
+constexpr int kLzBlk = 6;
+constexpr int kLzCols = 2 * kLzBlk;                   // columns per thread
 constexpr int kLzMaxNC = kLzCols * kLzThreads;
+static_assert(kLzMaxNC >= 4 * kMaxWords + 2, "column blocks cover the widest sum");
 constexpr int kStopBytes = 256;                       // stop flag and step count
 
 struct LzShared {
@@ -77,42 +85,83 @@ __device__ int lz_load(const uint64_t* src, int W, LzShared& sh, uint32_t* mag) 
   return neg ? -1 : 1;
 }
 
-// Adds sgn * a * b (magnitudes of na, nb limbs) to the per-thread column
-// sums lo / hi of columns k = t + T c: lo collects the low halves of the
+// First column of this thread's block q (0: block t, 1: block t + half), or
+// -1 if the thread has no such block.
+__device__ __forceinline__ int lz_block_start(int q, int NC) {
+  const int t = threadIdx.x;
+  const int nbk = (NC + kLzBlk - 1) / kLzBlk, half = (nbk + 1) / 2;
+  const int blk = q == 0 ? t : t + half;
+  const bool own = q == 0 ? t < half : blk < nbk;
+  return own ? blk * kLzBlk : -1;
+}
+
+// Adds sgn * a * b (magnitudes of na, nb limbs) to the column sums lo / hi
+// of this thread's blocks (columns < NC): lo collects the low halves of the
 // limb products a_i b_(k-i), hi their high halves (which belong to column
-// k + 1).
+// k + 1).  For a block k0 .. k0 + kLzBlk - 1 the b limbs a step needs,
+// b[k0 + c - i], shift by one place from one i to the next, so a window of
+// kLzBlk registers holds them (one new limb per step, steps unrolled in
+// groups of kLzBlk so that every slot is a fixed register) and a step costs
+// two LDS reads for kLzBlk independent limb products.  Out-of-range limbs
+// read as zero.
 __device__ __forceinline__ void lz_product(const uint32_t* a, int na, const uint32_t* b, int nb,
-                                           int sgn, int64_t* lo, int64_t* hi) {
-  const int T = blockDim.x, t = threadIdx.x;
+                                           int sgn, int NC, int64_t* lo, int64_t* hi) {
+  constexpr int B = kLzBlk;
 #pragma unroll
-  for (int c = 0; c < kLzCols; ++c) {
-    const int k = t + T * c;
-    const int i0 = k - nb + 1 > 0 ? k - nb + 1 : 0;
-    const int i1 = k < na - 1 ? k : na - 1;
-    uint64_t sl = 0, sh = 0;
-    for (int i = i0; i <= i1; ++i) {
-      const uint64_t p = (uint64_t)a[i] * (uint64_t)b[k - i];
-      sl += (uint32_t)p;
-      sh += p >> 32;
+  for (int q = 0; q < 2; ++q) {
+    const int k0 = lz_block_start(q, NC);
+    if (k0 < 0) continue;
+    const int ilo = max(0, k0 - nb + 1), ihi = min(na - 1, k0 + B - 1);
+    if (ilo > ihi) continue;
+    const int i0 = ilo - ilo % B;
+    uint64_t sl[B], sh[B];
+    uint32_t w[B];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      sl[c] = sh[c] = 0;
+      const int j = k0 + c - i0;                 // slot c holds b[k0 + c - i] for i = i0
+      w[c] = (c > 0 && j >= 0 && j < nb) ? b[j] : 0u;
     }
-    lo[c] += sgn * (int64_t)sl;
-    hi[c] += sgn * (int64_t)sh;
+    for (int ib = i0; ib <= ihi; ib += B) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int i = ib + u;
+        const int j = k0 - i;                    // the new limb, for column k0: slot (-i) mod B
+        w[(B - u) % B] = (j >= 0 && j < nb) ? b[j] : 0u;
+        const uint32_t ai = i <= ihi ? a[i] : 0u;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+          const uint64_t p = (uint64_t)ai * (uint64_t)w[(c - u + B) % B];
+          sl[c] += (uint32_t)p;
+          sh[c] += p >> 32;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      lo[q * B + c] += sgn * (int64_t)sl[c];
+      hi[q * B + c] += sgn * (int64_t)sh[c];
+    }
   }
 }
 
-// coef[k] = lo_k + hi_(k-1) for k < NC (the per-thread sums written out).
+// coef[k] = lo_k + hi_(k-1) for k < NC (the per-thread sums written out):
+// within a block directly, across a block boundary after a barrier (the
+// first column of every block receives from exactly one block).
 __device__ void lz_store_cols(const int64_t* lo, const int64_t* hi, int NC, LzShared& sh) {
-  const int T = blockDim.x, t = threadIdx.x;
 #pragma unroll
-  for (int c = 0; c < kLzCols; ++c) {
-    const int k = t + T * c;
-    if (k < NC) sh.coef[k] = lo[c];
+  for (int q = 0; q < 2; ++q) {
+    const int k0 = lz_block_start(q, NC);
+    if (k0 < 0) continue;
+#pragma unroll
+    for (int c = 0; c < kLzBlk; ++c)
+      if (k0 + c < NC) sh.coef[k0 + c] = lo[q * kLzBlk + c] + (c > 0 ? hi[q * kLzBlk + c - 1] : 0);
   }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < kLzCols; ++c) {
-    const int k = t + T * c;
-    if (k + 1 < NC) sh.coef[k + 1] += hi[c];
+  for (int q = 0; q < 2; ++q) {
+    const int k0 = lz_block_start(q, NC);
+    if (k0 >= 0 && k0 + kLzBlk < NC) sh.coef[k0 + kLzBlk] += hi[q * kLzBlk + kLzBlk - 1];
   }
   __syncthreads();
 }
@@ -196,7 +245,7 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_combine(LzCombine cmb, int n,
     if (!cmb.a[tm]) continue;
     const int sa = lz_load(cmb.a[tm], W, sh, sh.mag[0]);
     const int su = lz_load(cmb.u[tm] + (int64_t)i * W, W, sh, sh.mag[1]);
-    lz_product(sh.mag[0], NL, sh.mag[1], NL, cmb.sg[tm] * sa * su, lo, hi);
+    lz_product(sh.mag[0], NL, sh.mag[1], NL, cmb.sg[tm] * sa * su, NC, lo, hi);
     __syncthreads();
   }
   lz_store_cols(lo, hi, NC, sh);
@@ -224,7 +273,7 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_dot_part(const uint64_t* u, c
   for (int i = i0; i < i1; ++i) {
     const int su = lz_load(u + (int64_t)i * W, W, sh, sh.mag[0]);
     const int sv = lz_load(v + (int64_t)i * W, W, sh, sh.mag[1]);
-    lz_product(sh.mag[0], NL, sh.mag[1], NL, su * sv, lo, hi);
+    lz_product(sh.mag[0], NL, sh.mag[1], NL, su * sv, NC, lo, hi);
     __syncthreads();
   }
   lz_store_cols(lo, hi, NC, sh);
@@ -259,7 +308,7 @@ __device__ void lz_scalar_op(LzShared& sh, int W, int nl, int nx, int ny, int sg
   const int NC = 2 * nl + 2;
   int64_t lo[kLzCols], hi[kLzCols];
   lz_zero(lo, hi);
-  if (nx >= 0) lz_product(sh.mag[nx], nl, sh.mag[ny], nl, sgn, lo, hi);
+  if (nx >= 0) lz_product(sh.mag[nx], nl, sh.mag[ny], nl, sgn, NC, lo, hi);
   __syncthreads();
   lz_store_cols(lo, hi, NC, sh);
   if (addm >= 0) lz_add_shifted(sh.mag[addm], nl, addsgn, addshift, NC, sh);
@@ -336,7 +385,7 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
         const int NC = 2 * nl + 2;
         int64_t lo[kLzCols], hi[kLzCols];
         lz_zero(lo, hi);
-        lz_product(sh.mag[2], nl, sh.mag[3], nl, -s2, lo, hi);
+        lz_product(sh.mag[2], nl, sh.mag[3], nl, -s2, NC, lo, hi);
         __syncthreads();
         lz_store_cols(lo, hi, NC, sh);
         lz_add_shifted(sh.mag[2], nl, 1, p + 1, NC, sh);
