@@ -96,8 +96,8 @@ __device__ __forceinline__ int lz_block_start(int q, int NC) {
 }
 
 // Adds sgn * a * b (magnitudes of na, nb limbs) to the column sums lo / hi
-// of this thread's blocks (columns < NC): lo collects the low halves of the
-// limb products a_i b_(k-i), hi their high halves (which belong to column
+// of this thread's blocks (columns < NC): column k's sum of the limb
+// products a_i b_(k-i) is kept as lo_k + hi_k 2^32 (hi belongs to column
 // k + 1).  For a block k0 .. k0 + kLzBlk - 1 the b limbs a step needs,
 // b[k0 + c - i], shift by one place from one i to the next, so a window of
 // kLzBlk registers holds them (one new limb per step, steps unrolled in
@@ -114,11 +114,13 @@ __device__ __forceinline__ void lz_product(const uint32_t* a, int na, const uint
     const int ilo = max(0, k0 - nb + 1), ihi = min(na - 1, k0 + B - 1);
     if (ilo > ihi) continue;
     const int i0 = ilo - ilo % B;
-    uint64_t sl[B], sh[B];
+    // al / ah: sums of the products of a's low / high 16 bits (below
+    // kLzLimbs 2^48 < 2^59), one 64-bit multiply-add each
+    uint64_t al[B], ah[B];
     uint32_t w[B];
 #pragma unroll
     for (int c = 0; c < B; ++c) {
-      sl[c] = sh[c] = 0;
+      al[c] = ah[c] = 0;
       const int j = k0 + c - i0;                 // slot c holds b[k0 + c - i] for i = i0
       w[c] = (c > 0 && j >= 0 && j < nb) ? b[j] : 0u;
     }
@@ -129,18 +131,22 @@ __device__ __forceinline__ void lz_product(const uint32_t* a, int na, const uint
         const int j = k0 - i;                    // the new limb, for column k0: slot (-i) mod B
         w[(B - u) % B] = (j >= 0 && j < nb) ? b[j] : 0u;
         const uint32_t ai = i <= ihi ? a[i] : 0u;
+        const uint32_t alo = ai & 0xffffu, ahi = ai >> 16;
 #pragma unroll
         for (int c = 0; c < B; ++c) {
-          const uint64_t p = (uint64_t)ai * (uint64_t)w[(c - u + B) % B];
-          sl[c] += (uint32_t)p;
-          sh[c] += p >> 32;
+          const uint32_t wc = w[(c - u + B) % B];
+          al[c] += (uint64_t)alo * wc;
+          ah[c] += (uint64_t)ahi * wc;
         }
       }
     }
+    // column value al + ah 2^16 as lo (column k) + hi 2^32 (column k + 1)
 #pragma unroll
     for (int c = 0; c < B; ++c) {
-      lo[q * B + c] += sgn * (int64_t)sl[c];
-      hi[q * B + c] += sgn * (int64_t)sh[c];
+      const uint64_t l = (al[c] & 0xffffffffull) + ((ah[c] & 0xffffull) << 16);
+      const uint64_t h = (al[c] >> 32) + (ah[c] >> 16);
+      lo[q * B + c] += sgn * (int64_t)l;
+      hi[q * B + c] += sgn * (int64_t)h;
     }
   }
 }
