@@ -21,7 +21,8 @@
 // product in their own columns, signed int64 column sums); the shared
 // carry / round / pack step (limb width 32) then turns the column sums into
 // the rounded result.  Dot products sum the columns of many entries per
-// work-group and then across work-groups.
+// work-group, then add them into one shared column array with integer
+// atomics.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -265,9 +266,11 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_combine(LzCombine cmb, int n,
 }
 
 // Dot product, first stage: work-group g sums sgn |u_i| |v_i| over its
-// entries [g per, (g + 1) per) into column sums part[g][k].
+// entries [g per, (g + 1) per) into column sums and adds them to the shared
+// columns cols[k] (64-bit integer atomics: exact, so the order of the
+// work-groups does not matter).
 __global__ void __launch_bounds__(kLzThreads) k_lz_dot_part(const uint64_t* u, const uint64_t* v,
-                                                            int n, int W, int per, int64_t* part,
+                                                            int n, int W, int per, int64_t* cols,
                                                             const int* stop) {
   __shared__ LzShared sh;
   const int g = blockIdx.x;
@@ -283,21 +286,23 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_dot_part(const uint64_t* u, c
     __syncthreads();
   }
   lz_store_cols(lo, hi, NC, sh);
-  for (int k = threadIdx.x; k < NC; k += blockDim.x) part[(int64_t)g * NC + k] = sh.coef[k];
+  for (int k = threadIdx.x; k < NC; k += blockDim.x)
+    if (sh.coef[k])
+      atomicAdd(reinterpret_cast<unsigned long long*>(cols + k), (unsigned long long)sh.coef[k]);
 }
 
-// Second stage (one work-group): the column sums of all parts, rounded:
-// out = rne(sum_i u_i v_i).  count (if not null) counts the steps.
-__global__ void __launch_bounds__(kLzThreads) k_lz_dot_final(const int64_t* part, int G, int P,
-                                                             int W, uint64_t* out,
-                                                             const int* stop, int* count) {
+// Second stage (one work-group): the shared column sums, rounded:
+// out = rne(sum_i u_i v_i); the columns are zeroed again for the next dot
+// product.  count (if not null) counts the steps.
+__global__ void __launch_bounds__(kLzThreads) k_lz_dot_final(int64_t* cols, int P, int W,
+                                                             uint64_t* out, const int* stop,
+                                                             int* count) {
   __shared__ LzShared sh;
   if (*stop) return;
   const int NC = 4 * W + 2;
   for (int k = threadIdx.x; k < NC; k += blockDim.x) {
-    int64_t s = 0;
-    for (int g = 0; g < G; ++g) s += part[(int64_t)g * NC + k];
-    sh.coef[k] = s;
+    sh.coef[k] = cols[k];
+    cols[k] = 0;
   }
   __syncthreads();
   carry_round_pack_fit(sh.coef, NC, 32, P, W, sh.cs, out, sh.red);
@@ -414,12 +419,13 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
   for (int m = t; m < W; m += T) beta[m] = sh.out[m];
 }
 
-__global__ void k_lz_init(int* stop, uint64_t* zero, int W) {
+__global__ void k_lz_init(int* stop, uint64_t* zero, int W, int64_t* cols, int NC) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     stop[0] = 0;
     stop[1] = 0;
   }
   for (int m = threadIdx.x; m < W; m += blockDim.x) zero[m] = 0ull;
+  for (int k = threadIdx.x; k < NC; k += blockDim.x) cols[k] = 0;
 }
 
 __global__ void k_lz_count(const int* stop, int32_t* steps_done) {
@@ -435,7 +441,7 @@ __global__ void k_lz_copy(const uint64_t* src, uint64_t* dst, int64_t words, con
 
 struct LzLayout {
   int W, G, per, NC;
-  int64_t off_stop, off_zero, off_nu, off_rho, off_vec[3], off_part, off_mv, bytes;
+  int64_t off_stop, off_zero, off_nu, off_rho, off_vec[3], off_cols, off_mv, bytes;
 };
 
 LzLayout lz_layout(const hmv_plan* p) {
@@ -458,8 +464,8 @@ LzLayout lz_layout(const hmv_plan* p) {
     L.off_vec[k] = o;
     o += align_up(8 * n * L.W);
   }
-  L.off_part = o;
-  o += align_up(8 * (int64_t)L.G * L.NC);
+  L.off_cols = o;
+  o += align_up(8 * (int64_t)L.NC);
   L.off_mv = o;
   o += kStatusBytes + p->mv_scratch;
   L.bytes = o;
@@ -494,13 +500,13 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
   uint64_t* rho = reinterpret_cast<uint64_t*>(base + L.off_rho);
   uint64_t* vec[3];
   for (int k = 0; k < 3; ++k) vec[k] = reinterpret_cast<uint64_t*>(base + L.off_vec[k]);
-  int64_t* part = reinterpret_cast<int64_t*>(base + L.off_part);
+  int64_t* cols = reinterpret_cast<int64_t*>(base + L.off_cols);
   char* mv = base + L.off_mv;
   const int n = (int)p->n, W = L.W, P = p->P;
   const int64_t nw = (int64_t)n * W;
   hipError_t e = launch_clear_status(st, s);
   if (e != hipSuccess) return status_from_hip(e, "lanczos: clear status");
-  hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(256), 0, s, stop, zero, W);
+  hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(256), 0, s, stop, zero, W, cols, L.NC);
   e = hipMemcpyAsync(vec[0], q1, 8 * nw, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return status_from_hip(e, "lanczos: start vector");
   // vec[q] = q_j, vec[qp] = q_(j-1) (zero at first), vec[wv] = w, then r
@@ -520,9 +526,9 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
     if (rc != HMV_OK) return rc;
     // alpha_j = rne(q . w)
     hipLaunchKernelGGL(k_lz_dot_part, dim3(L.G), dim3(kLzThreads), 0, s, vec[q], vec[wv], n, W,
-                       L.per, part, stop);
-    hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, part, L.G, P, W,
-                       alpha_j, stop, stop + 1);
+                       L.per, cols, stop);
+    hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, cols, P, W, alpha_j,
+                       stop, stop + 1);
     // r = rne(w - alpha q_j - beta_j q_j-1), in place of w
     LzCombine c{};
     c.w = vec[wv];
@@ -538,9 +544,9 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
     hipLaunchKernelGGL(k_lz_combine, dim3(n), dim3(kLzThreads), 0, s, c, n, P, W, stop);
     // nu = rne(r . r); rho, beta_j+1 (or the stop)
     hipLaunchKernelGGL(k_lz_dot_part, dim3(L.G), dim3(kLzThreads), 0, s, vec[wv], vec[wv], n, W,
-                       L.per, part, stop);
-    hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, part, L.G, P, W, nu,
-                       stop, nullptr);
+                       L.per, cols, stop);
+    hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, cols, P, W, nu, stop,
+                       nullptr);
     hipLaunchKernelGGL(k_lz_scalars, dim3(1), dim3(kLzThreads), 0, s, nu, P, W, rho,
                        beta_j1, stop);
     // q_j+1 = clamp(rne(rho r)), in place of q_j-1
