@@ -23,8 +23,10 @@
 // the rounded result.  Dot products sum the columns of many entries per
 // work-group, then add them into one shared column array with integer
 // atomics.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cstdio>
 #include <new>
@@ -309,19 +311,73 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_dot_final(int64_t* cols, int 
   if (count && threadIdx.x == 0) *count += 1;
 }
 
-// The scalars of a step (one work-group): from nu, rho and beta, or the stop.
+// The scalars of a step run on G work-groups of a cooperative launch.  Each
+// work-group keeps every operand in its own LDS and repeats the small
+// operations itself (identical results, no communication).  A product of at
+// least kLzDistLimbs limbs is split: work-group g multiplies its slice of a
+// by b and adds its columns into a shared column array with integer atomics;
+// after one grid barrier every work-group reads the full sums back and
+// carries them itself.  Three arrays rotate: during product j the
+// work-groups zero array (j + 1) mod 3, which product j - 2 used and which
+// every work-group finished reading before the barrier of product j - 1.
+constexpr int kLzDistLimbs = 128;
+struct LzDist {
+  int64_t* cols;     // 3 x kLzMaxNC column sums
+  int k;             // distributed products so far (the rotation)
+};
+
+// sh.coef[0 .. NC) = the column sums of sgn * a * b (nl limbs each).
+__device__ void lz_product_cols(LzShared& sh, const uint32_t* a, const uint32_t* b, int nl,
+                                int sgn, int NC, LzDist& dist) {
+  const int G = gridDim.x, g = blockIdx.x, T = blockDim.x, t = threadIdx.x;
+  if (G == 1 || nl < kLzDistLimbs) {
+    int64_t lo[kLzCols], hi[kLzCols];
+    lz_zero(lo, hi);
+    lz_product(a, nl, b, nl, sgn, NC, lo, hi);
+    __syncthreads();
+    lz_store_cols(lo, hi, NC, sh);
+    return;
+  }
+  int64_t* cur = dist.cols + (int64_t)(dist.k % 3) * kLzMaxNC;
+  int64_t* nxt = dist.cols + (int64_t)((dist.k + 1) % 3) * kLzMaxNC;
+  ++dist.k;
+  const int chunk = (kLzMaxNC + G - 1) / G;
+  for (int e = g * chunk + t; e < min(kLzMaxNC, (g + 1) * chunk); e += T) nxt[e] = 0;
+  const int per = (nl + G - 1) / G, a0 = min(nl, g * per), na = min(nl, a0 + per) - a0;
+  if (na > 0) {
+    const int NCs = na + nl + 1;                 // this slice's columns, from column a0
+    int64_t lo[kLzCols], hi[kLzCols];
+    lz_zero(lo, hi);
+    lz_product(a + a0, na, b, nl, sgn, NCs, lo, hi);
+    __syncthreads();
+    lz_store_cols(lo, hi, NCs, sh);
+    for (int k = t; k < NCs; k += T)
+      if (sh.coef[k])
+        atomicAdd(reinterpret_cast<unsigned long long*>(cur + a0 + k),
+                  (unsigned long long)sh.coef[k]);
+  }
+  // release the zeroing stores and the atomics, meet, acquire the sums (the
+  // work-groups sit on different XCDs, whose L2s the fences keep coherent)
+  __threadfence();
+  cooperative_groups::this_grid().sync();
+  __threadfence();
+  for (int k = t; k < NC; k += T) sh.coef[k] = cur[k];
+  __syncthreads();
+}
+
 // A product of two numbers already in LDS (magnitudes mag[nx], mag[ny], nl
 // limbs each; nx < 0 for none) plus an optional shifted term addsgn
 // mag[addm] 2^addshift, rounded at `round` bits (0: exact); the result goes
 // to sh.out (W words).
 __device__ void lz_scalar_op(LzShared& sh, int W, int nl, int nx, int ny, int sgn, int addm,
-                             int addsgn, int addshift, int round) {
+                             int addsgn, int addshift, int round, LzDist& dist) {
   const int NC = 2 * nl + 2;
-  int64_t lo[kLzCols], hi[kLzCols];
-  lz_zero(lo, hi);
-  if (nx >= 0) lz_product(sh.mag[nx], nl, sh.mag[ny], nl, sgn, NC, lo, hi);
-  __syncthreads();
-  lz_store_cols(lo, hi, NC, sh);
+  if (nx >= 0) {
+    lz_product_cols(sh, sh.mag[nx], sh.mag[ny], nl, sgn, NC, dist);
+  } else {
+    for (int k = threadIdx.x; k < NC; k += blockDim.x) sh.coef[k] = 0;
+    __syncthreads();
+  }
   if (addm >= 0) lz_add_shifted(sh.mag[addm], nl, addsgn, addshift, NC, sh);
   carry_round_pack_fit(sh.coef, NC, 32, round, W, sh.cs, sh.out, sh.red);
 }
@@ -336,11 +392,15 @@ constexpr int kNewtonStartBits = 64, kNewtonStartSteps = 9, kNewtonFinalSteps = 
 
 __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, int P, int W,
                                                            uint64_t* rho, uint64_t* beta,
-                                                           int* stop) {
+                                                           int* stop, int64_t* dcols,
+                                                           int* dctr) {
   __shared__ LzShared sh;
   __shared__ int top;
   if (*stop) return;
   const int T = blockDim.x, t = threadIdx.x;
+  const bool lead = blockIdx.x == 0;             // the work-group that writes results
+  LzDist dist{dcols, *dctr};
+  const int k_start = dist.k;
   const int NLF = 2 * W;                         // full-precision limbs
   // mag[0] = N (nu's integer; nu >= 0)
   lz_load(nu, W, sh, sh.mag[0]);
@@ -352,16 +412,18 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
   const int64_t bits = top < 0 ? 0 : 32 * (int64_t)top + (32 - __clz((int)sh.mag[0][top]));
   // stop when nu < 2^-120, i.e. N < 2^(P - 120)
   if (top < 0 || bits - 1 < (int64_t)P - 120) {
-    for (int m = t; m < W; m += T) beta[m] = 0ull;
-    __syncthreads();
-    if (t == 0) *stop = 1;
+    if (lead) {
+      for (int m = t; m < W; m += T) beta[m] = 0ull;
+      __syncthreads();
+      if (t == 0) *stop = 1;
+    }
     return;
   }
   const int b = (int)(bits - P);                 // 2^(b-1) <= nu < 2^b
   const int s = b >= 0 ? (b + 1) / 2 : -((-b) / 2);   // ceil(b / 2)
   // mag[1] = M: mu = nu 4^-s at P bits, rounded when s > 0
-  if (s > 0) lz_scalar_op(sh, W, NLF, -1, -1, 1, 0, 1, 0, 2 * s);
-  else lz_scalar_op(sh, W, NLF, -1, -1, 1, 0, 1, -2 * s, 0);
+  if (s > 0) lz_scalar_op(sh, W, NLF, -1, -1, 1, 0, 1, 0, 2 * s, dist);
+  else lz_scalar_op(sh, W, NLF, -1, -1, 1, 0, 1, -2 * s, 0, dist);
   lz_load(sh.out, W, sh, sh.mag[1]);
   int p = P < kNewtonStartBits ? P : kNewtonStartBits, prev = 0;
   for (;;) {
@@ -377,28 +439,24 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
       }
       __syncthreads();
     } else {
-      lz_scalar_op(sh, W, nl, -1, -1, 1, 2, 1, p - prev, 0);
+      lz_scalar_op(sh, W, nl, -1, -1, 1, 2, 1, p - prev, 0, dist);
       lz_load(sh.out, W, sh, sh.mag[2]);
     }
     // mag[4] = mu_p: M rounded to p bits
-    if (p < P) lz_scalar_op(sh, W, NLF, -1, -1, 1, 1, 1, 0, P - p);
-    else lz_scalar_op(sh, W, NLF, -1, -1, 1, 1, 1, 0, 0);
+    if (p < P) lz_scalar_op(sh, W, NLF, -1, -1, 1, 1, 1, 0, P - p, dist);
+    else lz_scalar_op(sh, W, NLF, -1, -1, 1, 1, 1, 0, 0, dist);
     lz_load(sh.out, W, sh, sh.mag[4]);
     for (int it = 0; it < steps; ++it) {
       // t1 = rne(y y)          -> mag[3]
-      lz_scalar_op(sh, W, nl, 2, 2, 1, -1, 1, 0, p);
+      lz_scalar_op(sh, W, nl, 2, 2, 1, -1, 1, 0, p, dist);
       lz_load(sh.out, W, sh, sh.mag[3]);
       // t2 = rne(mu_p t1)      -> mag[3]
-      lz_scalar_op(sh, W, nl, 4, 3, 1, -1, 1, 0, p);
+      lz_scalar_op(sh, W, nl, 4, 3, 1, -1, 1, 0, p, dist);
       const int s2 = lz_load(sh.out, W, sh, sh.mag[3]);
       // y = rne((3 y 2^p - y t2) / 2): 3 y 2^p as y 2^(p+1) + y 2^p
       {
         const int NC = 2 * nl + 2;
-        int64_t lo[kLzCols], hi[kLzCols];
-        lz_zero(lo, hi);
-        lz_product(sh.mag[2], nl, sh.mag[3], nl, -s2, NC, lo, hi);
-        __syncthreads();
-        lz_store_cols(lo, hi, NC, sh);
+        lz_product_cols(sh, sh.mag[2], sh.mag[3], nl, -s2, NC, dist);
         lz_add_shifted(sh.mag[2], nl, 1, p + 1, NC, sh);
         lz_add_shifted(sh.mag[2], nl, 1, p, NC, sh);
         carry_round_pack_fit(sh.coef, NC, 32, p + 1, W, sh.cs, sh.out, sh.red);
@@ -410,22 +468,30 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
     p = 2 * p - 8 < P ? 2 * p - 8 : P;
   }
   // rho = y 2^-s (mag[2] -> mag[4] and rho)
-  if (s > 0) lz_scalar_op(sh, W, NLF, -1, -1, 1, 2, 1, 0, s);
-  else lz_scalar_op(sh, W, NLF, -1, -1, 1, 2, 1, -s, 0);
-  for (int m = t; m < W; m += T) rho[m] = sh.out[m];
+  if (s > 0) lz_scalar_op(sh, W, NLF, -1, -1, 1, 2, 1, 0, s, dist);
+  else lz_scalar_op(sh, W, NLF, -1, -1, 1, 2, 1, -s, 0, dist);
+  if (lead)
+    for (int m = t; m < W; m += T) rho[m] = sh.out[m];
   lz_load(sh.out, W, sh, sh.mag[4]);
   // beta = rne(N rho)
-  lz_scalar_op(sh, W, NLF, 0, 4, 1, -1, 1, 0, P);
-  for (int m = t; m < W; m += T) beta[m] = sh.out[m];
+  lz_scalar_op(sh, W, NLF, 0, 4, 1, -1, 1, 0, P, dist);
+  if (lead) {
+    for (int m = t; m < W; m += T) beta[m] = sh.out[m];
+    // every work-group read the counter before the first grid barrier
+    if (t == 0 && dist.k != k_start) *dctr = dist.k;
+  }
 }
 
-__global__ void k_lz_init(int* stop, uint64_t* zero, int W, int64_t* cols, int NC) {
+__global__ void k_lz_init(int* stop, uint64_t* zero, int W, int64_t* cols, int NC,
+                          int64_t* dcols) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     stop[0] = 0;
     stop[1] = 0;
+    stop[2] = 0;                                 // the rotation of the distributed products
   }
   for (int m = threadIdx.x; m < W; m += blockDim.x) zero[m] = 0ull;
   for (int k = threadIdx.x; k < NC; k += blockDim.x) cols[k] = 0;
+  for (int k = threadIdx.x; k < 3 * kLzMaxNC; k += blockDim.x) dcols[k] = 0;
 }
 
 __global__ void k_lz_count(const int* stop, int32_t* steps_done) {
@@ -439,9 +505,22 @@ __global__ void k_lz_copy(const uint64_t* src, uint64_t* dst, int64_t words, con
     dst[m] = src[m];
 }
 
+// Work-groups of the scalar kernel: up to 64, all resident at once.
+hipError_t lz_scalars_grid(int* grid) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_lz_scalars,
+                                                     kLzThreads, 0);
+  if (e != hipSuccess) return e;
+  *grid = std::max(1, std::min(64, per_cu * cus));
+  return hipSuccess;
+}
+
 struct LzLayout {
   int W, G, per, NC;
-  int64_t off_stop, off_zero, off_nu, off_rho, off_vec[3], off_cols, off_mv, bytes;
+  int64_t off_stop, off_zero, off_nu, off_rho, off_vec[3], off_cols, off_dcols, off_mv, bytes;
 };
 
 LzLayout lz_layout(const hmv_plan* p) {
@@ -466,6 +545,8 @@ LzLayout lz_layout(const hmv_plan* p) {
   }
   L.off_cols = o;
   o += align_up(8 * (int64_t)L.NC);
+  L.off_dcols = o;
+  o += align_up(8 * 3 * (int64_t)kLzMaxNC);
   L.off_mv = o;
   o += kStatusBytes + p->mv_scratch;
   L.bytes = o;
@@ -501,12 +582,17 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
   uint64_t* vec[3];
   for (int k = 0; k < 3; ++k) vec[k] = reinterpret_cast<uint64_t*>(base + L.off_vec[k]);
   int64_t* cols = reinterpret_cast<int64_t*>(base + L.off_cols);
+  int64_t* dcols = reinterpret_cast<int64_t*>(base + L.off_dcols);
+  int* dctr = stop + 2;
+  int sgrid = 0;
+  hipError_t ge = lz_scalars_grid(&sgrid);
+  if (ge != hipSuccess) return status_from_hip(ge, "lanczos: scalar grid");
   char* mv = base + L.off_mv;
   const int n = (int)p->n, W = L.W, P = p->P;
   const int64_t nw = (int64_t)n * W;
   hipError_t e = launch_clear_status(st, s);
   if (e != hipSuccess) return status_from_hip(e, "lanczos: clear status");
-  hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(256), 0, s, stop, zero, W, cols, L.NC);
+  hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(256), 0, s, stop, zero, W, cols, L.NC, dcols);
   e = hipMemcpyAsync(vec[0], q1, 8 * nw, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return status_from_hip(e, "lanczos: start vector");
   // vec[q] = q_j, vec[qp] = q_(j-1) (zero at first), vec[wv] = w, then r
@@ -547,8 +633,14 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
                        L.per, cols, stop);
     hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, cols, P, W, nu, stop,
                        nullptr);
-    hipLaunchKernelGGL(k_lz_scalars, dim3(1), dim3(kLzThreads), 0, s, nu, P, W, rho,
-                       beta_j1, stop);
+    {
+      const uint64_t* a_nu = nu;
+      void* args[] = {(void*)&a_nu, (void*)&P, (void*)&W, (void*)&rho, (void*)&beta_j1,
+                      (void*)&stop, (void*)&dcols, (void*)&dctr};
+      e = hipLaunchCooperativeKernel((const void*)k_lz_scalars, dim3(sgrid), dim3(kLzThreads),
+                                     args, 0, s);
+      if (e != hipSuccess) return status_from_hip(e, "lanczos: scalars");
+    }
     // q_j+1 = clamp(rne(rho r)), in place of q_j-1
     LzCombine d{};
     d.w = nullptr;
