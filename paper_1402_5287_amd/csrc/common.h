@@ -194,12 +194,23 @@ __device__ inline bool number_in_range(const uint64_t* wd, int W, int P) {
   return ok_hi || ok_sp;
 }
 
-// number_in_range evaluated by the calling wavefront alone (its 64 lanes
-// stride over the words): no block barrier, so the other waves go on.
-__device__ inline bool number_in_range_wave(const uint64_t* wd, int W, int P) {
+// The same test spread over every wave of the work-group, with no barrier
+// of its own.  rf: two LDS flags (every high bit equals the sign bit; the
+// number is 2^P) that thread 0 sets with range_flags_init before the
+// barrier which publishes the words; a wave holding a word that breaks a
+// test clears its flag.  After a later barrier range_flags_ok(rf) gives the
+// verdict.
+__device__ inline void range_flags_init(uint32_t* rf) {
+  if (threadIdx.x == 0) {
+    rf[0] = 1u;
+    rf[1] = 1u;
+  }
+}
+
+__device__ inline void range_check_block(const uint64_t* wd, int W, int P, uint32_t* rf) {
   const uint64_t sign = (wd[W - 1] >> 63) ? ~0ull : 0ull;
   int ok_hi = 1, ok_sp = (sign == 0ull);
-  for (int q = threadIdx.x & 63; q < W; q += 64) {
+  for (int q = threadIdx.x; q < W; q += blockDim.x) {
     const uint64_t word = wd[q];
     const int lo = q * 64;
     uint64_t mask;
@@ -210,8 +221,12 @@ __device__ inline bool number_in_range_wave(const uint64_t* wd, int W, int P) {
     const uint64_t expect = (q == (P >> 6)) ? (1ull << (P & 63)) : 0ull;
     if (word != expect) ok_sp = 0;
   }
-  return __all(ok_hi) || __all(ok_sp);
+  const bool lead = (threadIdx.x & 63) == 0;
+  if (!__all(ok_hi) && lead) rf[0] = 0u;
+  if (!__all(ok_sp) && lead) rf[1] = 0u;
 }
+
+__device__ inline bool range_flags_ok(const uint32_t* rf) { return (rf[0] | rf[1]) != 0u; }
 
 // raw (unsigned) w-bit field e of the sign-extended two's complement number
 __device__ inline uint32_t raw_digit(const uint64_t* wd, int W, uint64_t signw, int w, int e) {
@@ -229,8 +244,10 @@ constexpr int kSplitRegs = 16;
 // contiguous chunks of ceil(L / blockDim) digits; store(e, d) is called once
 // per digit.  The balancing carry c_{e+1} = [u_e + c_e >= 2^(w-1)] is resolved
 // with a block scan of generate / propagate / kill codes.  `lds` = 32 slots.
-// A chunk of at most kSplitRegs digits is read once, as one stream of bits
-// through a 128-bit window (one LDS word per 64 bits), and kept in registers.
+// A chunk of at most kSplitRegs digits is kept in registers; each field is
+// cut with one funnel shift from the aligned pair of 32-bit words that holds
+// it (w < 32), and all of a thread's reads are independent, so they are in
+// flight together.
 template <class Store>
 __device__ __forceinline__ void split_balanced(const uint64_t* wd, int W, int w, int L, Store store,
                                                uint32_t* lds) {
@@ -244,28 +261,23 @@ __device__ __forceinline__ void split_balanced(const uint64_t* wd, int W, int w,
   if (per <= kSplitRegs) {                       // uniform
     const int cnt = e1 > e0 ? e1 - e0 : 0;
     const uint32_t mask = (1u << w) - 1u;
+    const uint32_t* wd32 = reinterpret_cast<const uint32_t*>(wd);
+    const uint32_t sg = (uint32_t)signw;
+    const int nd = 2 * W;                        // 32-bit words of the number
     uint32_t u[kSplitRegs];
-    const int bit = e0 * w;
-    int q = bit >> 6;
-    unsigned __int128 acc = 0;
-    int avail = 0;
-    if (cnt > 0) {
-      acc = (unsigned __int128)((q < W ? wd[q] : signw) >> (bit & 63));
-      avail = 64 - (bit & 63);
-      ++q;
+    // field e: bits [e w, e w + w), past the words the sign fill; the
+    // addresses are clamped into the words, so every read is in bounds
+#pragma unroll
+    for (int j = 0; j < kSplitRegs; ++j) {
+      const int b = (e0 + j) * w, d = b >> 5;
+      const uint32_t lo = wd32[d < nd ? d : nd - 1];
+      const uint32_t hi = wd32[d + 1 < nd ? d + 1 : nd - 1];
+      u[j] = __builtin_amdgcn_alignbit(d + 1 < nd ? hi : sg, d < nd ? lo : sg, (uint32_t)b & 31u) &
+             mask;
     }
 #pragma unroll
     for (int j = 0; j < kSplitRegs; ++j) {
-      u[j] = 0u;
       if (j < cnt) {
-        if (avail < w) {
-          acc |= (unsigned __int128)(q < W ? wd[q] : signw) << avail;
-          avail += 64;
-          ++q;
-        }
-        u[j] = (uint32_t)acc & mask;
-        acc >>= w;
-        avail -= w;
         const uint32_t g = u[j] >= half ? 1u : (u[j] == half - 1u ? 2u : 0u);
         f = op(f, g);
       }

@@ -209,18 +209,18 @@ __global__ void __launch_bounds__(256, 2) k_rows_fwd(const uint64_t* __restrict_
   // the elements past the digits are zero (and the imaginary half of the
   // last one when L is odd), written while the words are in flight
   double* bd = reinterpret_cast<double*>(buf);
+  __shared__ uint32_t rf[2];
+  range_flags_init(rf);
   load_words_then(in + (int64_t)gather_row(r, gather_n) * W, W, wd, [&] {
     for (int k = (L + 1) / 2 + t; k < M; k += T) buf[lds_slot(k)] = make_double2(0.0, 0.0);
     if ((L & 1) && t == 0) bd[2 * lds_slot(L >> 1) + 1] = 0.0;
   });
   __syncthreads();
-  // range check by wave 0 alone (no block barrier)
-  if (t < 64) {
-    const bool ok = number_in_range_wave(wd, W, P);
-    if (!ok && t == 0) status_or(st, ST_RANGE);
-  }
+  // range check by every wave, read back after the split's barriers
+  range_check_block(wd, W, P, rf);
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
+  if (t == 0 && !range_flags_ok(rf)) status_or(st, ST_RANGE);
   fft_lds_t<LOGM>(buf, -1);
   if (pack) pack_real_row<true>(buf, M, out, r, rows_alloc, lt);
   else pack_real_row<false>(buf, M, out, r, rows_alloc, lt);
@@ -567,15 +567,16 @@ __device__ __forceinline__ void row_fwd3(const uint64_t* __restrict__ in, int W,
   uint64_t* wd = reinterpret_cast<uint64_t*>(buf + lds_points((L + 1) / 2));
   double2* bufA = buf;                              // K/2 points
   double2* bufB = buf + lds_points(KA);             // K points
+  __shared__ uint32_t rf[2];
+  range_flags_init(rf);
   load_words(in + (int64_t)gather_row(r, gather_n) * W, W, wd);
   __syncthreads();
-  if (t < 64) {
-    const bool ok = number_in_range_wave(wd, W, P);
-    if (!ok && t == 0) status_or(st, ST_RANGE);
-  }
+  // range check by every wave, read back after the split's barriers
+  range_check_block(wd, W, P, rf);
   split_balanced(wd, W, w, L, [&](int e, int d) { dig[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; },
                  red);
   __syncthreads();
+  if (t == 0 && !range_flags_ok(rf)) status_or(st, ST_RANGE);
   // radix-3 step: u0 exact (digit sums), u1 with one constant and one
   // tabulated root
   double u0[S];
@@ -1041,17 +1042,17 @@ __device__ __forceinline__ void b_row_fwd(const uint64_t* in, int W, int P, int 
   const int T = blockDim.x, t = threadIdx.x;
   const int M = 1 << logM;
   double* bd = reinterpret_cast<double*>(buf);
+  __shared__ uint32_t rf[2];
+  range_flags_init(rf);
   load_words_then(in + (int64_t)gather_row(r, gather_n) * W, W, wd, [&] {
     for (int k = (L + 1) / 2 + t; k < M; k += T) buf[lds_slot(k)] = make_double2(0.0, 0.0);
     if ((L & 1) && t == 0) bd[2 * lds_slot(L >> 1) + 1] = 0.0;
   });
   __syncthreads();
-  if (t < 64) {
-    const bool ok = number_in_range_wave(wd, W, P);
-    if (!ok && t == 0) status_or(st, ST_RANGE);
-  }
+  range_check_block(wd, W, P, rf);
   split_balanced(wd, W, w, L, [&](int e, int d) { bd[2 * lds_slot(e >> 1) + (e & 1)] = (double)d; }, red);
   __syncthreads();
+  if (t == 0 && !range_flags_ok(rf)) status_or(st, ST_RANGE);
   fft_lds(buf, logM, -1);
   pack_real_row<false>(buf, M, out, r, rows_alloc, 3);
   __syncthreads();

@@ -86,17 +86,17 @@ __global__ void __launch_bounds__(512) k_ntt_rows_fwd(const uint64_t* __restrict
   if (r >= count) return;
   const int T = blockDim.x, t = threadIdx.x, N = 1 << logN;
   // the residues past the digits are zeroed while the words are in flight;
-  // wave 0 alone checks the range (no block barrier)
+  // every wave checks part of the range, read back after the split's barriers
+  __shared__ uint32_t rf[2];
+  range_flags_init(rf);
   load_words_then(in + (int64_t)n_gather_row(r, gather_n) * W, W, wd, [&] {
     for (int e = L + t; e < N; e += T) nbuf[nswz(e)] = 0;
   });
   __syncthreads();
-  if (t < 64) {
-    const bool ok = number_in_range_wave(wd, W, P);
-    if (!ok && t == 0) status_or(st, ST_RANGE);
-  }
+  range_check_block(wd, W, P, rf);
   split_balanced(wd, W, w, L, [&](int e, int d) { nbuf[nswz(e)] = gl_from_int(d); }, red);
   __syncthreads();
+  if (t == 0 && !range_flags_ok(rf)) status_or(st, ST_RANGE);
   ntt_lds<0>(nbuf, logN);
   for (int k = t; k < N; k += T) out[ntile(k, r, rows_alloc, logT)] = nbuf[nswz(k)];
 }
