@@ -31,9 +31,12 @@ namespace {
 
 constexpr int kFxThreads = 256;
 
-// exps[0] = largest exponent of a nonzero entry, exps[1] = smallest,
-// exps[2] = 1 if a significand needs more than P bits
-__global__ void k_f_exp_init(int* exps) {
+// Clears the status block and starts exps: exps[0] = largest exponent of a
+// nonzero entry, exps[1] = smallest, exps[2] = 1 if a significand needs
+// more than P bits (one launch for both).
+__global__ void k_f_clear(DevStatus* st, int* exps) {
+  uint64_t* p = reinterpret_cast<uint64_t*>(st);
+  if (threadIdx.x < sizeof(DevStatus) / 8) p[threadIdx.x] = 0ull;
   if (threadIdx.x == 0) {
     exps[0] = INT_MIN;
     exps[1] = INT_MAX;
@@ -41,36 +44,60 @@ __global__ void k_f_exp_init(int* exps) {
   }
 }
 
-// One wavefront per number: is it nonzero, and does |M| < 2^P hold (every
-// bit from P up equal to the sign, and M != -2^P)?
+// Is each number nonzero, and does |M| < 2^P hold (every bit from P up equal
+// to the sign, and M != -2^P)?  A wavefront takes the numbers r = its index,
+// its index + the wavefronts of the grid, ...; the work-group combines its
+// wavefronts in LDS and makes one atomic update of each kind (one update
+// per number, all on the same words, would run one after another).
 __global__ void __launch_bounds__(kFxThreads) k_f_exp_range(const uint64_t* __restrict__ sig,
                                                             const int32_t* __restrict__ exp,
                                                             int count, int W, int P, int* exps) {
-  const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * (kFxThreads / 64) + (threadIdx.x >> 6);
-  if (r >= count) return;
-  const uint64_t* m = sig + (int64_t)r * W;
-  const uint64_t signw = (m[W - 1] >> 63) ? ~0ull : 0ull;
+  constexpr int kWaves = kFxThreads / 64;
+  __shared__ int red[3][kWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int pw = P >> 6, pb = P & 63;
-  int nz = 0, wide = 0, low_zero = 1;
-  for (int q = lane; q < W; q += 64) {
-    const uint64_t v = m[q];
-    if (v) nz = 1;
-    // bits at and above P must all equal the sign bit
-    uint64_t hi = q > pw ? v : (q == pw ? (pb ? v >> pb : v) : 0ull);
-    uint64_t ref = q > pw ? signw : (q == pw ? (pb ? signw >> pb : signw) : 0ull);
-    if (q >= pw && hi != ref) wide = 1;
-    // bits below P all zero (with a negative sign: M = -2^P)
-    const uint64_t lowbits = q < pw ? v : (q == pw ? (pb ? v & ((1ull << pb) - 1) : 0ull) : 0ull);
-    if (lowbits) low_zero = 0;
+  int emax = INT_MIN, emin = INT_MAX, bad = 0;
+  for (int r = blockIdx.x * kWaves + wv; r < count; r += gridDim.x * kWaves) {
+    const uint64_t* m = sig + (int64_t)r * W;
+    const uint64_t signw = (m[W - 1] >> 63) ? ~0ull : 0ull;
+    int nz = 0, wide = 0, low_zero = 1;
+#pragma unroll 4
+    for (int q = lane; q < W; q += 64) {
+      const uint64_t v = m[q];
+      if (v) nz = 1;
+      // bits at and above P must all equal the sign bit
+      const uint64_t hi = q > pw ? v : (q == pw ? (pb ? v >> pb : v) : 0ull);
+      const uint64_t ref = q > pw ? signw : (q == pw ? (pb ? signw >> pb : signw) : 0ull);
+      if (q >= pw && hi != ref) wide = 1;
+      // bits below P all zero (with a negative sign: M = -2^P)
+      const uint64_t lowbits = q < pw ? v : (q == pw ? (pb ? v & ((1ull << pb) - 1) : 0ull) : 0ull);
+      if (lowbits) low_zero = 0;
+    }
+    if (__any(nz)) {                        // uniform over the wavefront
+      if (__any(wide) || (signw && __all(low_zero))) bad = 1;
+      const int e = exp[r];
+      emax = max(emax, e);
+      emin = min(emin, e);
+    }
   }
-  nz = __any(nz);
-  wide = __any(wide);
-  low_zero = __all(low_zero);
-  if (lane == 0 && nz) {
-    if (wide || (signw && low_zero)) atomicOr(&exps[2], 1);
-    atomicMax(&exps[0], exp[r]);
-    atomicMin(&exps[1], exp[r]);
+  if (lane == 0) {
+    red[0][wv] = emax;
+    red[1][wv] = emin;
+    red[2][wv] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = INT_MIN, b = INT_MAX, c = 0;
+    for (int k = 0; k < kWaves; ++k) {
+      a = max(a, red[0][k]);
+      b = min(b, red[1][k]);
+      c |= red[2][k];
+    }
+    if (a != INT_MIN) {
+      atomicMax(&exps[0], a);
+      atomicMin(&exps[1], b);
+    }
+    if (c) atomicOr(&exps[2], 1);
   }
 }
 
@@ -116,55 +143,70 @@ __global__ void __launch_bounds__(kFxThreads) k_f_to_fixed(const uint64_t* __res
   }
 }
 
-// One work-group per row: the exact sum S (We words, two's complement) to
-// P significant bits, ties to even; significand in Wp words, exponent
-// E_h + E_x - 2Q + shift + P (zero: 0 and exponent 0).
+// LDS operations of a wavefront complete in issue order, so lanes of one
+// wavefront exchange LDS words with no barrier; the fences keep the
+// compiler's order of the accesses around the exchange.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One wavefront per row (blockDim.x / 64 rows per work-group, each with its
+// own We + Wp words of LDS; no block barrier): the exact sum S (We words,
+// two's complement) to P significant bits, ties to even; significand in Wp
+// words, exponent E_h + E_x - 2Q + shift + P (zero: 0 and exponent 0).
+// Lane l owns the words q = l, l + 64, ...; first / last words with a
+// property are wavefront minima / maxima of each lane's first / last hit.
 __global__ void __launch_bounds__(kFxThreads) k_f_from_exact(const uint64_t* __restrict__ S,
                                                              int count, int We, int P, int Wp,
                                                              int64_t ebase, const int* __restrict__ exps,
                                                              uint64_t* __restrict__ ysig,
                                                              int32_t* __restrict__ yexp,
                                                              DevStatus* st) {
-  extern __shared__ uint64_t mag[];         // We words, then Wp words of the result
-  __shared__ int first_nz, high_nz, sticky, first_not_ones, first_res_nz;
+  extern __shared__ uint64_t lds[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r = blockIdx.x * (int)(blockDim.x >> 6) + wv;
+  if (r >= count) return;                   // whole wavefronts; nothing waits on them
+  uint64_t* mag = lds + (int64_t)wv * (We + Wp);
   uint64_t* res = mag + We;
-  const int r = blockIdx.x;
-  if (r >= count) return;
-  const int T = blockDim.x, t = threadIdx.x;
   const uint64_t* src = S + (int64_t)r * We;
   const bool neg = (src[We - 1] >> 63) != 0;
-  if (t == 0) {
-    first_nz = We;
-    high_nz = -1;
-    sticky = 0;
-    first_not_ones = Wp;
-    first_res_nz = Wp;
-  }
-  __syncthreads();
-  for (int q = t; q < We; q += T) {
+  int f = We;                                // first nonzero word
+#pragma unroll 4
+  for (int q = lane; q < We; q += 64) {
     const uint64_t v = src[q];
     mag[q] = v;
-    if (v) atomicMin(&first_nz, q);
+    if (v && f == We) f = q;
   }
-  __syncthreads();
+  f = wave_min(f);
   // magnitude: -S = ~S + 1, i.e. zeros below the first nonzero word f, -S_f
-  // there and ~S above
-  if (neg) {
-    const int f = first_nz;
-    for (int q = t; q < We; q += T) {
-      const uint64_t v = mag[q];
-      mag[q] = q < f ? 0ull : (q == f ? (0ull - v) : ~v);
+  // there and ~S above (each lane rewrites its own words)
+  int hw = -1;                               // highest nonzero word
+  for (int q = lane; q < We; q += 64) {
+    uint64_t v = mag[q];
+    if (neg) {
+      v = q < f ? 0ull : (q == f ? (0ull - v) : ~v);
+      mag[q] = v;
     }
+    if (v) hw = q;
   }
-  __syncthreads();
-  for (int q = t; q < We; q += T)
-    if (mag[q]) atomicMax(&high_nz, q);
-  __syncthreads();
-  const int hw = high_nz;
+  hw = wave_max(hw);
+  wave_sync();
   uint64_t* outs = ysig + (int64_t)r * Wp;
   if (hw < 0) {                              // S = 0
-    for (int q = t; q < Wp; q += T) outs[q] = 0ull;
-    if (t == 0) yexp[r] = 0;
+    for (int q = lane; q < Wp; q += 64) outs[q] = 0ull;
+    if (lane == 0) yexp[r] = 0;
     return;
   }
   const int64_t b = 64 * (int64_t)hw + (64 - __clzll((long long)mag[hw]));   // bit length
@@ -185,68 +227,69 @@ __global__ void __launch_bounds__(kFxThreads) k_f_from_exact(const uint64_t* __r
     const int64_t rb = shift - 1;
     const int rq = (int)(rb >> 6), ro = (int)(rb & 63);
     int st_mine = 0;
-    for (int q = t; q <= rq; q += T) {
+    for (int q = lane; q <= rq; q += 64) {
       const uint64_t v = q < rq ? mag[q] : (ro ? mag[q] & ((1ull << ro) - 1) : 0ull);
       if (v) st_mine = 1;
     }
-    if (st_mine) sticky = 1;
-    __syncthreads();
+    const int sticky = __any(st_mine);
     const int rbit = (int)((mag[rq] >> ro) & 1ull);
     const int lsb = (int)((bits_at(shift) & 1ull));
     up = rbit && (sticky || lsb);
   }
   // P significant bits: bits [shift, shift + P) of the magnitude
   const int pw = P >> 6, pb = P & 63;
-  for (int q = t; q < Wp; q += T) {
+  int fno = Wp;                              // first word that is not all ones
+  for (int q = lane; q < Wp; q += 64) {
     uint64_t v = bits_at(shift + 64 * (int64_t)q);
     if (q > pw || (q == pw && pb == 0)) v = 0ull;
     else if (q == pw) v &= (1ull << pb) - 1;
     res[q] = v;
-    if (up && v != ~0ull) atomicMin(&first_not_ones, q);
+    if (v != ~0ull && fno == Wp) fno = q;
   }
-  __syncthreads();
-  if (up) {
+  if (up) {                                  // uniform over the wavefront
     // increment: the words below the first one that is not all ones become 0
-    const int f = first_not_ones;
-    for (int q = t; q <= f && q < Wp; q += T) res[q] = q < f ? 0ull : res[q] + 1ull;
-    __syncthreads();
+    fno = wave_min(fno);
+    for (int q = lane; q <= fno && q < Wp; q += 64) res[q] = q < fno ? 0ull : res[q] + 1ull;
+    wave_sync();
     // a carry into bit P: the significand was 2^P - 1, now 2^P -> 2^(P-1)
     if ((res[pw] >> pb) & 1ull) {
-      for (int q = t; q < Wp; q += T) res[q] = 0ull;
-      __syncthreads();
-      if (t == 0) res[(P - 1) >> 6] = 1ull << ((P - 1) & 63);
+      for (int q = lane; q < Wp; q += 64) res[q] = 0ull;
+      wave_sync();
+      if (lane == 0) res[(P - 1) >> 6] = 1ull << ((P - 1) & 63);
       shift += 1;
     }
-    __syncthreads();
+    wave_sync();
   }
   // sign: two's complement over Wp words
   if (neg) {
-    for (int q = t; q < Wp; q += T)
-      if (res[q]) atomicMin(&first_res_nz, q);
-    __syncthreads();
-    const int f = first_res_nz;
-    for (int q = t; q < Wp; q += T) {
+    int fr = Wp;
+    for (int q = lane; q < Wp; q += 64)
+      if (res[q] && fr == Wp) fr = q;
+    fr = wave_min(fr);
+    for (int q = lane; q < Wp; q += 64) {
       const uint64_t v = res[q];
-      outs[q] = q < f ? 0ull : (q == f ? (0ull - v) : ~v);
+      outs[q] = q < fr ? 0ull : (q == fr ? (0ull - v) : ~v);
     }
   } else {
-    for (int q = t; q < Wp; q += T) outs[q] = res[q];
+    for (int q = lane; q < Wp; q += 64) outs[q] = res[q];
   }
-  if (t == 0) {
+  if (lane == 0) {
     const int64_t e = ebase + (int64_t)exps[0] + shift + P;
     if (e > INT_MAX || e < INT_MIN) status_or(st, ST_OVERFLOW);
     yexp[r] = (int32_t)(e > INT_MAX ? INT_MAX : (e < INT_MIN ? INT_MIN : e));
   }
 }
 
-hipError_t exp_range(const uint64_t* sig, const int32_t* exp, int count, int W, int P, int* exps,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_f_exp_init, dim3(1), dim3(64), 0, s, exps);
+// status cleared, then the exponent range of `count` numbers into exps
+hipError_t clear_and_exp_range(const uint64_t* sig, const int32_t* exp, int count, int W, int P,
+                               int* exps, DevStatus* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_f_clear, dim3(1), dim3(64), 0, s, st, exps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || count <= 0) return e;
   const int per = kFxThreads / 64;
-  hipLaunchKernelGGL(k_f_exp_range, dim3((count + per - 1) / per), dim3(kFxThreads), 0, s, sig,
-                     exp, count, W, P, exps);
+  const int blocks = (count + per - 1) / per;
+  hipLaunchKernelGGL(k_f_exp_range, dim3(blocks < 256 ? blocks : 256), dim3(kFxThreads), 0, s,
+                     sig, exp, count, W, P, exps);
   return hipGetLastError();
 }
 
@@ -261,10 +304,14 @@ hipError_t to_fixed(const uint64_t* sig, const int32_t* exp, int count, int Wp, 
 hipError_t from_exact(const uint64_t* S, int count, int We, int P, int Wp, int64_t ebase,
                       const int* exps, uint64_t* ysig, int32_t* yexp, DevStatus* st,
                       hipStream_t s) {
-  const size_t lds = sizeof(uint64_t) * (size_t)(We + Wp);
-  if (lds > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_f_from_exact, dim3(count), dim3(kFxThreads), lds, s, S, count, We, P, Wp,
-                     ebase, exps, ysig, yexp, st);
+  // one wavefront per row, up to four per work-group within 64 KiB of LDS
+  const size_t per_row = sizeof(uint64_t) * (size_t)(We + Wp);
+  if (per_row > 64 * 1024) return hipErrorInvalidValue;
+  if (count <= 0) return hipSuccess;
+  int rows = (int)((64 * 1024) / per_row);
+  rows = rows < kFxThreads / 64 ? rows : kFxThreads / 64;
+  hipLaunchKernelGGL(k_f_from_exact, dim3((count + rows - 1) / rows), dim3(64 * rows),
+                     per_row * rows, s, S, count, We, P, Wp, ebase, exps, ysig, yexp, st);
   return hipGetLastError();
 }
 
@@ -345,8 +392,7 @@ int hmv_fplan_h(hmv_fplan** out, int kind, const uint64_t* h_sig, const int32_t*
   uint64_t* Hq = reinterpret_cast<uint64_t*>(base + kStatusBytes + kExpBytes);
   const int64_t hl = kind == HMV_CIRCULANT ? n : 2 * n - 1;
   char* inner_ws = base + z.plan_ws - z.inner_ws;
-  hipError_t e = launch_clear_status(st, s);
-  if (e == hipSuccess) e = exp_range(h_sig, h_exp, (int)hl, z.Wp, P, exps, s);
+  hipError_t e = clear_and_exp_range(h_sig, h_exp, (int)hl, z.Wp, P, exps, st, s);
   int host[3] = {0, 0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(host, exps, sizeof(host), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -389,8 +435,7 @@ int hmv_fplan_matvec(const hmv_fplan* p, const uint64_t* x_sig, const int32_t* x
   uint64_t* Xq = reinterpret_cast<uint64_t*>(base + z.off_fixed);
   uint64_t* Se = reinterpret_cast<uint64_t*>(base + z.off_exact);
   const int n = (int)p->n;
-  hipError_t e = launch_clear_status(st, s);
-  if (e == hipSuccess) e = exp_range(x_sig, x_exp, n, z.Wp, p->P, exps, s);
+  hipError_t e = clear_and_exp_range(x_sig, x_exp, n, z.Wp, p->P, exps, st, s);
   if (e == hipSuccess) e = to_fixed(x_sig, x_exp, n, z.Wp, p->D, z.Wq, exps, Xq, st, s);
   if (e != hipSuccess) return status_from_hip(e, "float matvec: alignment of x");
   // exact sums S_i = sum_j H_{i+j} X_j (carry step without rounding)
