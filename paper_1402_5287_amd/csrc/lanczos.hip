@@ -64,9 +64,36 @@ struct LzShared {
   int first_nz;
 };
 
+// LDS of the update kernel: two operands at a time, the column sums, the
+// carry scratch, and the rounded result in the words buffer's place (the
+// last load ends before the carry writes it): about 42 KB, three work-groups
+// per CU.
+struct LzCombShared {
+  union {
+    uint64_t wbuf[kMaxWords];
+    uint64_t out[kMaxWords];
+  };
+  uint32_t mag[2][kLzLimbs];
+  int64_t coef[kLzMaxNC + 2];
+  int64_t cs[kLzThreads + 8];
+  uint32_t red[32];
+  int first_nz;
+};
+
+// LDS of the dot-product kernel: its two operands and the column sums only
+// (about 39 KB, against about 63 KB of LzShared), so that four work-groups
+// fit on a CU.
+struct LzDotShared {
+  uint64_t wbuf[kMaxWords];
+  uint32_t mag[2][kLzLimbs];
+  int64_t coef[kLzMaxNC + 2];
+  int first_nz;
+};
+
 // Loads W two's complement words and stores the magnitude's 2W 32-bit limbs
 // in mag; returns the sign (+1 / -1; +1 for zero).  Every thread calls it.
-__device__ int lz_load(const uint64_t* src, int W, LzShared& sh, uint32_t* mag) {
+template <class SH>
+__device__ int lz_load(const uint64_t* src, int W, SH& sh, uint32_t* mag) {
   const int T = blockDim.x, t = threadIdx.x;
   if (t == 0) sh.first_nz = W;
   for (int q = t; q < W; q += T) sh.wbuf[q] = src[q];
@@ -157,7 +184,8 @@ __device__ __forceinline__ void lz_product(const uint32_t* a, int na, const uint
 // coef[k] = lo_k + hi_(k-1) for k < NC (the per-thread sums written out):
 // within a block directly, across a block boundary after a barrier (the
 // first column of every block receives from exactly one block).
-__device__ void lz_store_cols(const int64_t* lo, const int64_t* hi, int NC, LzShared& sh) {
+template <class SH>
+__device__ void lz_store_cols(const int64_t* lo, const int64_t* hi, int NC, SH& sh) {
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int k0 = lz_block_start(q, NC);
@@ -177,8 +205,8 @@ __device__ void lz_store_cols(const int64_t* lo, const int64_t* hi, int NC, LzSh
 
 // coef += sgn * |m| 2^shift (m: n limbs), split at the 32-bit column
 // boundaries (two passes, so that no two threads add to one column at once).
-__device__ void lz_add_shifted(const uint32_t* m, int n, int sgn, int shift, int NC,
-                               LzShared& sh) {
+template <class SH>
+__device__ void lz_add_shifted(const uint32_t* m, int n, int sgn, int shift, int NC, SH& sh) {
   const int T = blockDim.x, t = threadIdx.x;
   const int q = shift >> 5, r = shift & 31;
   for (int pass = 0; pass < 2; ++pass) {
@@ -211,7 +239,8 @@ struct LzCombine {
   int clamp;
 };
 
-__device__ void lz_clamp_store(LzShared& sh, int P, int W, uint64_t* dst) {
+template <class SH>
+__device__ void lz_clamp_store(SH& sh, int P, int W, uint64_t* dst) {
   // floor(v / 2^P) from bits [P, P + 64) (and all higher words equal to its
   // sign extension); v > 2^P or v < -2^P become +-2^P
   const int T = blockDim.x, t = threadIdx.x;
@@ -244,7 +273,7 @@ __device__ void lz_clamp_store(LzShared& sh, int P, int W, uint64_t* dst) {
 
 __global__ void __launch_bounds__(kLzThreads) k_lz_combine(LzCombine cmb, int n, int P, int W,
                                                            const int* stop) {
-  __shared__ LzShared sh;
+  __shared__ LzCombShared sh;
   const int i = blockIdx.x;
   if (i >= n || *stop) return;
   const int NL = 2 * W, NC = 2 * NL + 2;
@@ -259,8 +288,8 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_combine(LzCombine cmb, int n,
   }
   lz_store_cols(lo, hi, NC, sh);
   if (cmb.ew) {
-    const int sw = lz_load(cmb.w + (int64_t)i * W, W, sh, sh.mag[2]);
-    lz_add_shifted(sh.mag[2], NL, sw, P, NC, sh);
+    const int sw = lz_load(cmb.w + (int64_t)i * W, W, sh, sh.mag[0]);
+    lz_add_shifted(sh.mag[0], NL, sw, P, NC, sh);
   }
   uint64_t* dst = cmb.out + (int64_t)i * W;
   carry_round_pack_fit(sh.coef, NC, 32, P, W, sh.cs, cmb.clamp ? sh.out : dst, sh.red);
@@ -274,7 +303,7 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_combine(LzCombine cmb, int n,
 __global__ void __launch_bounds__(kLzThreads) k_lz_dot_part(const uint64_t* u, const uint64_t* v,
                                                             int n, int W, int per, int64_t* cols,
                                                             const int* stop) {
-  __shared__ LzShared sh;
+  __shared__ LzDotShared sh;
   const int g = blockIdx.x;
   if (*stop) return;
   const int NL = 2 * W, NC = 2 * NL + 2;
@@ -528,7 +557,7 @@ LzLayout lz_layout(const hmv_plan* p) {
   const int64_t n = p->n;
   L.W = (int)words_of(p->P);
   L.NC = 4 * L.W + 2;
-  L.G = (int)(n < 256 ? n : 256);
+  L.G = (int)(n < 1024 ? n : 1024);
   L.per = (int)((n + L.G - 1) / L.G);
   int64_t o = kStatusBytes;
   L.off_stop = o;
