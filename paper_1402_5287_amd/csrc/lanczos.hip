@@ -411,6 +411,71 @@ __device__ void lz_scalar_op(LzShared& sh, int W, int nl, int nx, int ny, int sg
   carry_round_pack_fit(sh.coef, NC, 32, round, W, sh.cs, sh.out, sh.red);
 }
 
+// mag[dst] = rne(A 2^(sl - sr)) as 2W = NL limbs, for A = mag[src] (its
+// first na limbs; A >= 0; sl or sr is 0): the value that the carry step
+// gives for the column sums of A shifted, rounded at sr bits, but cut
+// straight from the limbs (one funnel shift per limb, the round and sticky
+// bits, an increment that ripples through the lowest all-ones limbs), with
+// no column array.  src may be dst.  Every thread calls it.
+__device__ void lz_shift_round(LzShared& sh, int src, int na, int dst, int sl, int sr, int NL) {
+  constexpr int kPer = (kLzLimbs + kLzThreads - 1) / kLzThreads;
+  const int T = blockDim.x, t = threadIdx.x;
+  const uint32_t* a = sh.mag[src];
+  uint32_t* o = sh.mag[dst];
+  auto bits32 = [&](int64_t b) -> uint32_t {        // bits [b, b + 32) of A
+    if (b <= -32) return 0u;
+    if (b < 0) return na > 0 ? a[0] << (-b) : 0u;
+    const int64_t q = b >> 5;
+    const int r = (int)(b & 31);
+    const uint32_t lo = q < na ? a[q] >> r : 0u;
+    const uint32_t hi = (r && q + 1 < na) ? a[q + 1] << (32 - r) : 0u;
+    return lo | hi;
+  };
+  const int d = sl - sr;
+  uint32_t ov[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int k = t + T * j;
+    ov[j] = k < NL ? bits32(32 * (int64_t)k - d) : 0u;
+  }
+  int up = 0;
+  if (d < 0) {                                       // uniform
+    // round bit r - 1, sticky bits below it, last kept bit r
+    const int r = -d, rq = (r - 1) >> 5, rr = (r - 1) & 31;
+    int st = 0;
+    for (int l = t; l <= rq && l < na; l += T) {
+      const uint32_t v = l < rq ? a[l] : (a[l] & ((1u << rr) - 1u));
+      if (v) st = 1;
+    }
+    const int sticky = __syncthreads_or(st);
+    const int rbit = rq < na ? (int)((a[rq] >> rr) & 1u) : 0;
+    const int lsb = (int)(bits32(r) & 1u);
+    up = rbit && (sticky || lsb);
+  }
+  if (t == 0) sh.first_nz = NL;
+  __syncthreads();                                   // A read in full (src may be dst)
+  int fno = NL;                                      // first limb that is not all ones
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int k = t + T * j;
+    if (k < NL) {
+      o[k] = ov[j];
+      if (ov[j] != 0xffffffffu && k < fno) fno = k;
+    }
+  }
+  if (up) {                                          // uniform
+    if (fno < NL) atomicMin(&sh.first_nz, fno);
+    __syncthreads();
+    const int f = sh.first_nz;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int k = t + T * j;
+      if (k < NL && k <= f) o[k] = k < f ? 0u : ov[j] + 1u;
+    }
+  }
+  __syncthreads();
+}
+
 // Limbs that hold the values of a Newton step at working precision p (every
 // operand below 2^(p+4) in magnitude, with one limb to spare).
 __device__ __forceinline__ int lz_newton_limbs(int p) { return (p + 4 + 31) / 32 + 1; }
@@ -451,9 +516,7 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
   const int b = (int)(bits - P);                 // 2^(b-1) <= nu < 2^b
   const int s = b >= 0 ? (b + 1) / 2 : -((-b) / 2);   // ceil(b / 2)
   // mag[1] = M: mu = nu 4^-s at P bits, rounded when s > 0
-  if (s > 0) lz_scalar_op(sh, W, NLF, -1, -1, 1, 0, 1, 0, 2 * s, dist);
-  else lz_scalar_op(sh, W, NLF, -1, -1, 1, 0, 1, -2 * s, 0, dist);
-  lz_load(sh.out, W, sh, sh.mag[1]);
+  lz_shift_round(sh, 0, NLF, 1, s > 0 ? 0 : -2 * s, s > 0 ? 2 * s : 0, NLF);
   int p = P < kNewtonStartBits ? P : kNewtonStartBits, prev = 0;
   for (;;) {
     const int nl = lz_newton_limbs(p);
@@ -468,13 +531,10 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
       }
       __syncthreads();
     } else {
-      lz_scalar_op(sh, W, nl, -1, -1, 1, 2, 1, p - prev, 0, dist);
-      lz_load(sh.out, W, sh, sh.mag[2]);
+      lz_shift_round(sh, 2, nl, 2, p - prev, 0, NLF);
     }
     // mag[4] = mu_p: M rounded to p bits
-    if (p < P) lz_scalar_op(sh, W, NLF, -1, -1, 1, 1, 1, 0, P - p, dist);
-    else lz_scalar_op(sh, W, NLF, -1, -1, 1, 1, 1, 0, 0, dist);
-    lz_load(sh.out, W, sh, sh.mag[4]);
+    lz_shift_round(sh, 1, NLF, 4, 0, p < P ? P - p : 0, NLF);
     for (int it = 0; it < steps; ++it) {
       // t1 = rne(y y)          -> mag[3]
       lz_scalar_op(sh, W, nl, 2, 2, 1, -1, 1, 0, p, dist);
