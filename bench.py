@@ -545,7 +545,7 @@ def section_float(dev, h_words, xs, n, P, spread=64, steps=50):
     ys = torch.zeros((n, W), dtype=torch.int64, device=dev)
     ye = torch.zeros(n, dtype=torch.int32, device=dev)
     for k in range(3):
-        fplan.matvec(xs[k], xe[k], ys, ye)
+        fplan.matvec(xs[k % xs.shape[0]], xe[k % xs.shape[0]], ys, ye)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
