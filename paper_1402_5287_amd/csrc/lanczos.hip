@@ -476,6 +476,67 @@ __device__ void lz_shift_round(LzShared& sh, int src, int na, int dst, int sl, i
   __syncthreads();
 }
 
+// Non-negative integers below 2^256 as four 64-bit words, for the first
+// Newton level (p = 64: every operand below 2^68, every product below 2^136).
+struct LzU256 {
+  uint64_t w[4];
+};
+
+__device__ __forceinline__ LzU256 lz_mul128(unsigned __int128 a, unsigned __int128 b) {
+  const uint64_t a0 = (uint64_t)a, a1 = (uint64_t)(a >> 64);
+  const uint64_t b0 = (uint64_t)b, b1 = (uint64_t)(b >> 64);
+  const unsigned __int128 p00 = (unsigned __int128)a0 * b0, p01 = (unsigned __int128)a0 * b1;
+  const unsigned __int128 p10 = (unsigned __int128)a1 * b0, p11 = (unsigned __int128)a1 * b1;
+  LzU256 r;
+  r.w[0] = (uint64_t)p00;
+  unsigned __int128 m = (p00 >> 64) + (uint64_t)p01 + (uint64_t)p10;
+  r.w[1] = (uint64_t)m;
+  m = (m >> 64) + (p01 >> 64) + (p10 >> 64) + (uint64_t)p11;
+  r.w[2] = (uint64_t)m;
+  r.w[3] = (uint64_t)((m >> 64) + (p11 >> 64));
+  return r;
+}
+
+// rne(v / 2^k) for 64 <= k < 128 and a quotient below 2^128
+__device__ __forceinline__ unsigned __int128 lz_rne_shift(const LzU256& v, int k) {
+  const int r = k - 64;
+  const uint64_t lo = r ? (v.w[1] >> r) | (v.w[2] << (64 - r)) : v.w[1];
+  const uint64_t hi = r ? (v.w[2] >> r) | (v.w[3] << (64 - r)) : v.w[2];
+  const unsigned __int128 q = ((unsigned __int128)hi << 64) | lo;
+  // round bit k - 1 and the sticky bits below it
+  const uint64_t rbit = r ? (v.w[1] >> (r - 1)) & 1u : v.w[0] >> 63;
+  const bool sticky = r ? (v.w[0] != 0 || (v.w[1] & ((1ull << (r - 1)) - 1)) != 0)
+                        : (v.w[0] & ~(1ull << 63)) != 0;
+  return q + ((rbit && (sticky || (lo & 1u))) ? 1u : 0u);
+}
+
+// The first Newton level's steps on 128-bit words, by one thread: the same
+// roundings as the general steps (t1 = rne(y y / 2^64), t2 = rne(mu t1 /
+// 2^64), y = rne((3 y 2^64 - y t2) / 2^65), every value non-negative:
+// mu >= 2^62 and, after the first step, mu y^2 <= 2^128 < 3 2^128), without a
+// block barrier per product.
+__device__ unsigned __int128 lz_newton64(unsigned __int128 y, unsigned __int128 mu, int steps) {
+  for (int it = 0; it < steps; ++it) {
+    const unsigned __int128 t1 = lz_rne_shift(lz_mul128(y, y), 64);
+    const unsigned __int128 t2 = lz_rne_shift(lz_mul128(mu, t1), 64);
+    const LzU256 yt = lz_mul128(y, t2);
+    const unsigned __int128 y3 = 3 * y;          // below 2^70
+    // S = 3 y 2^64 - y t2 (>= 0), words [0, lo(y3), hi(y3), 0] minus yt
+    LzU256 S;
+    const uint64_t a[4] = {0ull, (uint64_t)y3, (uint64_t)(y3 >> 64), 0ull};
+    uint64_t borrow = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t d = a[q] - yt.w[q];
+      const uint64_t b1 = a[q] < yt.w[q];
+      S.w[q] = d - borrow;
+      borrow = b1 | (d < borrow);
+    }
+    y = lz_rne_shift(S, 65);
+  }
+  return y;
+}
+
 // Limbs that hold the values of a Newton step at working precision p (every
 // operand below 2^(p+4) in magnitude, with one limb to spare).
 __device__ __forceinline__ int lz_newton_limbs(int p) { return (p + 4 + 31) / 32 + 1; }
@@ -535,7 +596,20 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
     }
     // mag[4] = mu_p: M rounded to p bits
     lz_shift_round(sh, 1, NLF, 4, 0, p < P ? P - p : 0, NLF);
-    for (int it = 0; it < steps; ++it) {
+    if (prev == 0 && p == 64) {
+      // the first level in one thread (y and mu_p in limbs 0..3, the rest zero)
+      if (t == 0) {
+        auto u128_at = [&](const uint32_t* m) {
+          return ((unsigned __int128)(((uint64_t)m[3] << 32) | m[2]) << 64) |
+                 (((uint64_t)m[1] << 32) | m[0]);
+        };
+        const unsigned __int128 y = lz_newton64(u128_at(sh.mag[2]), u128_at(sh.mag[4]), steps);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sh.mag[2][q] = (uint32_t)(y >> (32 * q));
+      }
+      __syncthreads();
+    }
+    for (int it = 0; it < (prev == 0 && p == 64 ? 0 : steps); ++it) {
       // t1 = rne(y y)          -> mag[3]
       lz_scalar_op(sh, W, nl, 2, 2, 1, -1, 1, 0, p, dist);
       lz_load(sh.out, W, sh, sh.mag[3]);
