@@ -476,65 +476,110 @@ __device__ void lz_shift_round(LzShared& sh, int src, int na, int dst, int sl, i
   __syncthreads();
 }
 
-// Non-negative integers below 2^256 as four 64-bit words, for the first
-// Newton level (p = 64: every operand below 2^68, every product below 2^136).
-struct LzU256 {
-  uint64_t w[4];
-};
-
-__device__ __forceinline__ LzU256 lz_mul128(unsigned __int128 a, unsigned __int128 b) {
-  const uint64_t a0 = (uint64_t)a, a1 = (uint64_t)(a >> 64);
-  const uint64_t b0 = (uint64_t)b, b1 = (uint64_t)(b >> 64);
-  const unsigned __int128 p00 = (unsigned __int128)a0 * b0, p01 = (unsigned __int128)a0 * b1;
-  const unsigned __int128 p10 = (unsigned __int128)a1 * b0, p11 = (unsigned __int128)a1 * b1;
-  LzU256 r;
-  r.w[0] = (uint64_t)p00;
-  unsigned __int128 m = (p00 >> 64) + (uint64_t)p01 + (uint64_t)p10;
-  r.w[1] = (uint64_t)m;
-  m = (m >> 64) + (p01 >> 64) + (p10 >> 64) + (uint64_t)p11;
-  r.w[2] = (uint64_t)m;
-  r.w[3] = (uint64_t)((m >> 64) + (p11 >> 64));
-  return r;
+// The first Newton levels on 64-bit words, by one thread, with every size
+// and shift fixed at compile time (the words stay in registers): NW words
+// hold every operand of the level at PB bits (below 2^(PB+6) <= 2^(64 NW)),
+// products take 2 NW words.  Same roundings as the general steps, every
+// value non-negative: mu_PB >= 2^(PB-2) and, after the first step,
+// mu y^2 <= 2^(2 PB) (1 + tiny) < 3 2^(2 PB).
+template <int NW>
+__device__ __forceinline__ void lz_mulw(const uint64_t (&a)[NW], const uint64_t (&b)[NW],
+                                        uint64_t (&r)[2 * NW]) {
+#pragma unroll
+  for (int i = 0; i < 2 * NW; ++i) r[i] = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) {
+    uint64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const unsigned __int128 v = (unsigned __int128)a[i] * b[j] + r[i + j] + c;
+      r[i + j] = (uint64_t)v;
+      c = (uint64_t)(v >> 64);
+    }
+    r[i + NW] = c;
+  }
 }
 
-// rne(v / 2^k) for 64 <= k < 128 and a quotient below 2^128
-__device__ __forceinline__ unsigned __int128 lz_rne_shift(const LzU256& v, int k) {
-  const int r = k - 64;
-  const uint64_t lo = r ? (v.w[1] >> r) | (v.w[2] << (64 - r)) : v.w[1];
-  const uint64_t hi = r ? (v.w[2] >> r) | (v.w[3] << (64 - r)) : v.w[2];
-  const unsigned __int128 q = ((unsigned __int128)hi << 64) | lo;
-  // round bit k - 1 and the sticky bits below it
-  const uint64_t rbit = r ? (v.w[1] >> (r - 1)) & 1u : v.w[0] >> 63;
-  const bool sticky = r ? (v.w[0] != 0 || (v.w[1] & ((1ull << (r - 1)) - 1)) != 0)
-                        : (v.w[0] & ~(1ull << 63)) != 0;
-  return q + ((rbit && (sticky || (lo & 1u))) ? 1u : 0u);
+// q = rne(v / 2^K), 0 < K <= 64 NW, the quotient below 2^(64 NW)
+template <int NW, int K>
+__device__ __forceinline__ void lz_rnew(const uint64_t (&v)[2 * NW], uint64_t (&q)[NW]) {
+  constexpr int ws = K >> 6, bs = K & 63;
+  constexpr int rw = (K - 1) >> 6, rb = (K - 1) & 63;
+#pragma unroll
+  for (int m = 0; m < NW; ++m) {
+    const uint64_t lo = v[m + ws];
+    const uint64_t hi = m + ws + 1 < 2 * NW ? v[m + ws + 1] : 0ull;
+    q[m] = bs ? (lo >> bs) | (hi << ((64 - bs) & 63)) : lo;
+  }
+  const uint64_t rbit = (v[rw] >> rb) & 1u;
+  bool sticky = rb ? (v[rw] & ((1ull << rb) - 1)) != 0 : false;
+#pragma unroll
+  for (int m = 0; m < rw; ++m) sticky = sticky || v[m] != 0;
+  uint64_t c = (rbit && (sticky || (q[0] & 1u))) ? 1u : 0u;
+#pragma unroll
+  for (int m = 0; m < NW; ++m) {
+    q[m] += c;
+    c = (c && q[m] == 0) ? 1u : 0u;
+  }
 }
 
-// The first Newton level's steps on 128-bit words, by one thread: the same
-// roundings as the general steps (t1 = rne(y y / 2^64), t2 = rne(mu t1 /
-// 2^64), y = rne((3 y 2^64 - y t2) / 2^65), every value non-negative:
-// mu >= 2^62 and, after the first step, mu y^2 <= 2^128 < 3 2^128), without a
-// block barrier per product.
-__device__ unsigned __int128 lz_newton64(unsigned __int128 y, unsigned __int128 mu, int steps) {
+// steps Newton steps at PB bits: t1 = rne(y y / 2^PB), t2 = rne(mu t1 /
+// 2^PB), y = rne((3 y 2^PB - y t2) / 2^(PB+1))
+template <int NW, int PB>
+__device__ void lz_newton_words(uint64_t (&y)[NW], const uint64_t (&mu)[NW], int steps) {
+  static_assert(PB + 6 <= 64 * NW && PB + 1 <= 64 * NW, "the level fits its words");
   for (int it = 0; it < steps; ++it) {
-    const unsigned __int128 t1 = lz_rne_shift(lz_mul128(y, y), 64);
-    const unsigned __int128 t2 = lz_rne_shift(lz_mul128(mu, t1), 64);
-    const LzU256 yt = lz_mul128(y, t2);
-    const unsigned __int128 y3 = 3 * y;          // below 2^70
-    // S = 3 y 2^64 - y t2 (>= 0), words [0, lo(y3), hi(y3), 0] minus yt
-    LzU256 S;
-    const uint64_t a[4] = {0ull, (uint64_t)y3, (uint64_t)(y3 >> 64), 0ull};
+    uint64_t pr[2 * NW], t1[NW], t2[NW];
+    lz_mulw<NW>(y, y, pr);
+    lz_rnew<NW, PB>(pr, t1);
+    lz_mulw<NW>(mu, t1, pr);
+    lz_rnew<NW, PB>(pr, t2);
+    lz_mulw<NW>(y, t2, pr);                      // y t2
+    uint64_t y3[NW];                             // 3 y, below 2^(PB+6)
+    {
+      uint64_t c = 0;
+#pragma unroll
+      for (int m = 0; m < NW; ++m) {
+        const unsigned __int128 v = (unsigned __int128)y[m] * 3u + c;
+        y3[m] = (uint64_t)v;
+        c = (uint64_t)(v >> 64);
+      }
+    }
+    // S = 3 y 2^PB - y t2 (>= 0)
+    uint64_t S[2 * NW];
+    constexpr int ws = PB >> 6, bs = PB & 63;
     uint64_t borrow = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint64_t d = a[q] - yt.w[q];
-      const uint64_t b1 = a[q] < yt.w[q];
-      S.w[q] = d - borrow;
+    for (int m = 0; m < 2 * NW; ++m) {
+      const int src = m - ws;
+      const uint64_t lo = src >= 0 && src < NW ? y3[src] : 0ull;
+      const uint64_t lo1 = src - 1 >= 0 && src - 1 < NW ? y3[src - 1] : 0ull;
+      const uint64_t a = bs ? (lo << bs) | (lo1 >> ((64 - bs) & 63)) : lo;
+      const uint64_t d = a - pr[m];
+      const uint64_t b1 = a < pr[m];
+      S[m] = d - borrow;
       borrow = b1 | (d < borrow);
     }
-    y = lz_rne_shift(S, 65);
+    lz_rnew<NW, PB + 1>(S, y);
   }
-  return y;
+}
+
+// One thread: the Newton steps of level PB on y = mag[2], mu_PB = mag[4]
+// (the first 2 NW limbs of each; the limbs above are zero and stay so).
+template <int NW, int PB>
+__device__ void lz_newton_level(LzShared& sh, int steps) {
+  uint64_t y[NW], mu[NW];
+#pragma unroll
+  for (int m = 0; m < NW; ++m) {
+    y[m] = ((uint64_t)sh.mag[2][2 * m + 1] << 32) | sh.mag[2][2 * m];
+    mu[m] = ((uint64_t)sh.mag[4][2 * m + 1] << 32) | sh.mag[4][2 * m];
+  }
+  lz_newton_words<NW, PB>(y, mu, steps);
+#pragma unroll
+  for (int m = 0; m < NW; ++m) {
+    sh.mag[2][2 * m] = (uint32_t)y[m];
+    sh.mag[2][2 * m + 1] = (uint32_t)(y[m] >> 32);
+  }
 }
 
 // Limbs that hold the values of a Newton step at working precision p (every
@@ -596,20 +641,18 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
     }
     // mag[4] = mu_p: M rounded to p bits
     lz_shift_round(sh, 1, NLF, 4, 0, p < P ? P - p : 0, NLF);
-    if (prev == 0 && p == 64) {
-      // the first level in one thread (y and mu_p in limbs 0..3, the rest zero)
+    // the levels up to 456 bits (every one of them below P) in one thread
+    const bool small = (prev == 0 && p == 64) || (P > 456 && (p == 120 || p == 232 || p == 456));
+    if (small) {
       if (t == 0) {
-        auto u128_at = [&](const uint32_t* m) {
-          return ((unsigned __int128)(((uint64_t)m[3] << 32) | m[2]) << 64) |
-                 (((uint64_t)m[1] << 32) | m[0]);
-        };
-        const unsigned __int128 y = lz_newton64(u128_at(sh.mag[2]), u128_at(sh.mag[4]), steps);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) sh.mag[2][q] = (uint32_t)(y >> (32 * q));
+        if (p == 64) lz_newton_level<2, 64>(sh, steps);
+        else if (p == 120) lz_newton_level<2, 120>(sh, steps);
+        else if (p == 232) lz_newton_level<4, 232>(sh, steps);
+        else lz_newton_level<8, 456>(sh, steps);
       }
       __syncthreads();
     }
-    for (int it = 0; it < (prev == 0 && p == 64 ? 0 : steps); ++it) {
+    for (int it = 0; it < (small ? 0 : steps); ++it) {
       // t1 = rne(y y)          -> mag[3]
       lz_scalar_op(sh, W, nl, 2, 2, 1, -1, 1, 0, p, dist);
       lz_load(sh.out, W, sh, sh.mag[3]);
