@@ -296,19 +296,39 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_combine(LzCombine cmb, int n,
   if (cmb.clamp) lz_clamp_store(sh, P, W, dst);
 }
 
-// Dot product, first stage: work-group g sums sgn |u_i| |v_i| over its
-// entries [g per, (g + 1) per) into column sums and adds them to the shared
-// columns cols[k] (64-bit integer atomics: exact, so the order of the
-// work-groups does not matter).
+// Dot product, first stage: the column sums of sgn |u_i| |v_i| added into the
+// shared columns cols[k] (64-bit integer atomics: exact, so the order of the
+// work-groups does not matter).  With slices = 1, work-group g takes the
+// entries [g per, (g + 1) per); with slices = S > 1 (few entries), work-group
+// g takes slice g mod S of the limbs of u_i, i = g / S, times all of v_i, so
+// that n S work-groups share the products.
 __global__ void __launch_bounds__(kLzThreads) k_lz_dot_part(const uint64_t* u, const uint64_t* v,
-                                                            int n, int W, int per, int64_t* cols,
-                                                            const int* stop) {
+                                                            int n, int W, int per, int slices,
+                                                            int64_t* cols, const int* stop) {
   __shared__ LzDotShared sh;
   const int g = blockIdx.x;
   if (*stop) return;
   const int NL = 2 * W, NC = 2 * NL + 2;
   int64_t lo[kLzCols], hi[kLzCols];
   lz_zero(lo, hi);
+  if (slices > 1) {                                  // uniform
+    const int i = g / slices, sl = g - i * slices;
+    if (i >= n) return;                              // whole work-groups
+    const int su = lz_load(u + (int64_t)i * W, W, sh, sh.mag[0]);
+    const int sv = lz_load(v + (int64_t)i * W, W, sh, sh.mag[1]);
+    const int pl = (NL + slices - 1) / slices, a0 = min(NL, sl * pl);
+    const int na = min(NL, a0 + pl) - a0;
+    if (na <= 0) return;
+    const int NCs = na + NL + 1;                     // this slice's columns, from column a0
+    lz_product(sh.mag[0] + a0, na, sh.mag[1], NL, su * sv, NCs, lo, hi);
+    __syncthreads();
+    lz_store_cols(lo, hi, NCs, sh);
+    for (int k = threadIdx.x; k < NCs; k += blockDim.x)
+      if (sh.coef[k])
+        atomicAdd(reinterpret_cast<unsigned long long*>(cols + a0 + k),
+                  (unsigned long long)sh.coef[k]);
+    return;
+  }
   const int i0 = g * per, i1 = min(n, i0 + per);
   for (int i = i0; i < i1; ++i) {
     const int su = lz_load(u + (int64_t)i * W, W, sh, sh.mag[0]);
@@ -725,7 +745,7 @@ hipError_t lz_scalars_grid(int* grid) {
 }
 
 struct LzLayout {
-  int W, G, per, NC;
+  int W, G, per, slices, NC;
   int64_t off_stop, off_zero, off_nu, off_rho, off_vec[3], off_cols, off_dcols, off_mv, bytes;
 };
 
@@ -734,7 +754,10 @@ LzLayout lz_layout(const hmv_plan* p) {
   const int64_t n = p->n;
   L.W = (int)words_of(p->P);
   L.NC = 4 * L.W + 2;
-  L.G = (int)(n < 1024 ? n : 1024);
+  // dot products: one work-group per entry up to 1024 entries, and for fewer
+  // than 512 entries each product split over up to 16 work-groups
+  L.slices = n >= 512 ? 1 : (int)std::min<int64_t>(16, 1024 / n);
+  L.G = L.slices > 1 ? (int)(n * L.slices) : (int)(n < 1024 ? n : 1024);
   L.per = (int)((n + L.G - 1) / L.G);
   int64_t o = kStatusBytes;
   L.off_stop = o;
@@ -818,7 +841,7 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
     if (rc != HMV_OK) return rc;
     // alpha_j = rne(q . w)
     hipLaunchKernelGGL(k_lz_dot_part, dim3(L.G), dim3(kLzThreads), 0, s, vec[q], vec[wv], n, W,
-                       L.per, cols, stop);
+                       L.per, L.slices, cols, stop);
     hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, cols, P, W, alpha_j,
                        stop, stop + 1);
     // r = rne(w - alpha q_j - beta_j q_j-1), in place of w
@@ -836,7 +859,7 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
     hipLaunchKernelGGL(k_lz_combine, dim3(n), dim3(kLzThreads), 0, s, c, n, P, W, stop);
     // nu = rne(r . r); rho, beta_j+1 (or the stop)
     hipLaunchKernelGGL(k_lz_dot_part, dim3(L.G), dim3(kLzThreads), 0, s, vec[wv], vec[wv], n, W,
-                       L.per, cols, stop);
+                       L.per, L.slices, cols, stop);
     hipLaunchKernelGGL(k_lz_dot_final, dim3(1), dim3(kLzThreads), 0, s, cols, P, W, nu, stop,
                        nullptr);
     {
