@@ -296,6 +296,62 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_combine(LzCombine cmb, int n,
   if (cmb.clamp) lz_clamp_store(sh, P, W, dst);
 }
 
+// The same update for few entries, in two kernels.  Part: n S work-groups;
+// work-group g takes slice g mod S of the limbs of the scalar a[t] (all
+// terms t) times entry i = g / S of u[t], and adds its column sums into the
+// entry's own column array ccols + i NC (integer atomics, exact in any
+// order).  Final: one work-group per entry takes the columns (and zeroes them
+// for the next update), adds w, and carries, rounds and stores as above.
+__global__ void __launch_bounds__(kLzThreads) k_lz_combine_part(LzCombine cmb, int n, int W,
+                                                                int slices, int64_t* ccols,
+                                                                const int* stop) {
+  __shared__ LzDotShared sh;
+  const int g = blockIdx.x;
+  const int i = g / slices, sl = g - i * slices;
+  if (i >= n || *stop) return;
+  const int NL = 2 * W, NC = 2 * NL + 2;
+  const int pl = (NL + slices - 1) / slices, a0 = min(NL, sl * pl);
+  const int na = min(NL, a0 + pl) - a0;
+  if (na <= 0) return;
+  const int NCs = na + NL + 1;                       // this slice's columns, from column a0
+  int64_t lo[kLzCols], hi[kLzCols];
+  lz_zero(lo, hi);
+  for (int tm = 0; tm < 2; ++tm) {
+    if (!cmb.a[tm]) continue;
+    const int sa = lz_load(cmb.a[tm], W, sh, sh.mag[0]);
+    const int su = lz_load(cmb.u[tm] + (int64_t)i * W, W, sh, sh.mag[1]);
+    lz_product(sh.mag[0] + a0, na, sh.mag[1], NL, cmb.sg[tm] * sa * su, NCs, lo, hi);
+    __syncthreads();
+  }
+  lz_store_cols(lo, hi, NCs, sh);
+  int64_t* dst = ccols + (int64_t)i * NC + a0;
+  for (int k = threadIdx.x; k < NCs; k += blockDim.x)
+    if (sh.coef[k])
+      atomicAdd(reinterpret_cast<unsigned long long*>(dst + k), (unsigned long long)sh.coef[k]);
+}
+
+__global__ void __launch_bounds__(kLzThreads) k_lz_combine_final(LzCombine cmb, int n, int P,
+                                                                 int W, int64_t* ccols,
+                                                                 const int* stop) {
+  __shared__ LzCombShared sh;
+  const int i = blockIdx.x;
+  if (i >= n || *stop) return;
+  const int NL = 2 * W, NC = 2 * NL + 2;
+  int64_t* src = ccols + (int64_t)i * NC;
+  for (int k = threadIdx.x; k < NC; k += blockDim.x) {
+    sh.coef[k] = src[k];
+    src[k] = 0;
+  }
+  __syncthreads();
+  if (cmb.ew) {
+    const int sw = lz_load(cmb.w + (int64_t)i * W, W, sh, sh.mag[0]);
+    lz_add_shifted(sh.mag[0], NL, sw, P, NC, sh);
+  }
+  uint64_t* dst = cmb.out + (int64_t)i * W;
+  carry_round_pack_fit(sh.coef, NC, 32, P, W, sh.cs, cmb.clamp ? sh.out : dst, sh.red);
+  if (cmb.clamp) lz_clamp_store(sh, P, W, dst);
+}
+
 // Dot product, first stage: the column sums of sgn |u_i| |v_i| added into the
 // shared columns cols[k] (64-bit integer atomics: exact, so the order of the
 // work-groups does not matter).  With slices = 1, work-group g takes the
@@ -709,7 +765,7 @@ __global__ void __launch_bounds__(kLzThreads) k_lz_scalars(const uint64_t* nu, i
 }
 
 __global__ void k_lz_init(int* stop, uint64_t* zero, int W, int64_t* cols, int NC,
-                          int64_t* dcols) {
+                          int64_t* dcols, int64_t* ccols, int64_t nccols) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     stop[0] = 0;
     stop[1] = 0;
@@ -718,6 +774,9 @@ __global__ void k_lz_init(int* stop, uint64_t* zero, int W, int64_t* cols, int N
   for (int m = threadIdx.x; m < W; m += blockDim.x) zero[m] = 0ull;
   for (int k = threadIdx.x; k < NC; k += blockDim.x) cols[k] = 0;
   for (int k = threadIdx.x; k < 3 * kLzMaxNC; k += blockDim.x) dcols[k] = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nccols;
+       k += (int64_t)gridDim.x * blockDim.x)
+    ccols[k] = 0;
 }
 
 __global__ void k_lz_count(const int* stop, int32_t* steps_done) {
@@ -746,7 +805,8 @@ hipError_t lz_scalars_grid(int* grid) {
 
 struct LzLayout {
   int W, G, per, slices, NC;
-  int64_t off_stop, off_zero, off_nu, off_rho, off_vec[3], off_cols, off_dcols, off_mv, bytes;
+  int64_t off_stop, off_zero, off_nu, off_rho, off_vec[3], off_cols, off_dcols, off_ccols, nccols,
+      off_mv, bytes;
 };
 
 LzLayout lz_layout(const hmv_plan* p) {
@@ -776,10 +836,28 @@ LzLayout lz_layout(const hmv_plan* p) {
   o += align_up(8 * (int64_t)L.NC);
   L.off_dcols = o;
   o += align_up(8 * 3 * (int64_t)kLzMaxNC);
+  // per-entry column arrays of the split updates (fewer than 512 entries)
+  L.nccols = L.slices > 1 ? n * (int64_t)L.NC : 0;
+  L.off_ccols = o;
+  o += align_up(8 * L.nccols);
   L.off_mv = o;
   o += kStatusBytes + p->mv_scratch;
   L.bytes = o;
   return L;
+}
+
+// An entry update: one work-group per entry, or for fewer than 512 entries
+// the split form (n S partial work-groups, then one per entry).
+void lz_launch_combine(const LzCombine& c, int n, int P, int W, const LzLayout& L,
+                       int64_t* ccols, const int* stop, hipStream_t s) {
+  if (L.slices > 1) {
+    hipLaunchKernelGGL(k_lz_combine_part, dim3(n * L.slices), dim3(kLzThreads), 0, s, c, n, W,
+                       L.slices, ccols, stop);
+    hipLaunchKernelGGL(k_lz_combine_final, dim3(n), dim3(kLzThreads), 0, s, c, n, P, W, ccols,
+                       stop);
+  } else {
+    hipLaunchKernelGGL(k_lz_combine, dim3(n), dim3(kLzThreads), 0, s, c, n, P, W, stop);
+  }
 }
 
 }  // namespace
@@ -821,7 +899,9 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
   const int64_t nw = (int64_t)n * W;
   hipError_t e = launch_clear_status(st, s);
   if (e != hipSuccess) return status_from_hip(e, "lanczos: clear status");
-  hipLaunchKernelGGL(k_lz_init, dim3(1), dim3(256), 0, s, stop, zero, W, cols, L.NC, dcols);
+  int64_t* ccols = reinterpret_cast<int64_t*>(base + L.off_ccols);
+  hipLaunchKernelGGL(k_lz_init, dim3(L.nccols > 0 ? 64 : 1), dim3(256), 0, s, stop, zero, W, cols,
+                     L.NC, dcols, ccols, L.nccols);
   e = hipMemcpyAsync(vec[0], q1, 8 * nw, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return status_from_hip(e, "lanczos: start vector");
   // vec[q] = q_j, vec[qp] = q_(j-1) (zero at first), vec[wv] = w, then r
@@ -856,7 +936,7 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
     c.sg[1] = -1;
     c.out = vec[wv];
     c.clamp = 0;
-    hipLaunchKernelGGL(k_lz_combine, dim3(n), dim3(kLzThreads), 0, s, c, n, P, W, stop);
+    lz_launch_combine(c, n, P, W, L, ccols, stop, s);
     // nu = rne(r . r); rho, beta_j+1 (or the stop)
     hipLaunchKernelGGL(k_lz_dot_part, dim3(L.G), dim3(kLzThreads), 0, s, vec[wv], vec[wv], n, W,
                        L.per, L.slices, cols, stop);
@@ -879,7 +959,7 @@ int hmv_lanczos(const hmv_plan* p, const uint64_t* q1, int32_t steps, uint64_t* 
     d.sg[0] = 1;
     d.out = vec[qp];
     d.clamp = 1;
-    hipLaunchKernelGGL(k_lz_combine, dim3(n), dim3(kLzThreads), 0, s, d, n, P, W, stop);
+    lz_launch_combine(d, n, P, W, L, ccols, stop, s);
     e = hipGetLastError();
     if (e != hipSuccess) return status_from_hip(e, "lanczos step");
     const int nq = qp;
