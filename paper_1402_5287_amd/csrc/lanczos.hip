@@ -117,12 +117,15 @@ __device__ int lz_load(const uint64_t* src, int W, SH& sh, uint32_t* mag) {
 
 // First column of this thread's block q (0: block t, 1: block t + half), or
 // -1 if the thread has no such block.
-__device__ __forceinline__ int lz_block_start(int q, int NC) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ int lz_block_start(int q, int NC, int t) {
   const int nbk = (NC + kLzBlk - 1) / kLzBlk, half = (nbk + 1) / 2;
   const int blk = q == 0 ? t : t + half;
   const bool own = q == 0 ? t < half : blk < nbk;
   return own ? blk * kLzBlk : -1;
+}
+
+__device__ __forceinline__ int lz_block_start(int q, int NC) {
+  return lz_block_start(q, NC, (int)threadIdx.x);
 }
 
 // Adds sgn * a * b (magnitudes of na, nb limbs) to the column sums lo / hi
@@ -134,12 +137,17 @@ __device__ __forceinline__ int lz_block_start(int q, int NC) {
 // groups of kLzBlk so that every slot is a fixed register) and a step costs
 // two LDS reads for kLzBlk independent limb products.  Out-of-range limbs
 // read as zero.
+// (t: the thread's index among the threads that share the product; every
+// block of the NC columns belongs to one of them when they number at least
+// half the blocks.)
 __device__ __forceinline__ void lz_product(const uint32_t* a, int na, const uint32_t* b, int nb,
-                                           int sgn, int NC, int64_t* lo, int64_t* hi) {
+                                           int sgn, int NC, int64_t* lo, int64_t* hi,
+                                           int t = -1) {
   constexpr int B = kLzBlk;
+  if (t < 0) t = (int)threadIdx.x;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int k0 = lz_block_start(q, NC);
+    const int k0 = lz_block_start(q, NC, t);
     if (k0 < 0) continue;
     const int ilo = max(0, k0 - nb + 1), ihi = min(na - 1, k0 + B - 1);
     if (ilo > ihi) continue;
@@ -436,11 +444,42 @@ __device__ void lz_product_cols(LzShared& sh, const uint32_t* a, const uint32_t*
                                 int sgn, int NC, LzDist& dist) {
   const int G = gridDim.x, g = blockIdx.x, T = blockDim.x, t = threadIdx.x;
   if (G == 1 || nl < kLzDistLimbs) {
-    int64_t lo[kLzCols], hi[kLzCols];
-    lz_zero(lo, hi);
-    lz_product(a, nl, b, nl, sgn, NC, lo, hi);
+    // few columns leave most threads without a block: then S groups of
+    // T / S threads take one slice of a's limbs each and add their columns
+    // into sh.coef with 64-bit LDS atomics
+    const int half = ((NC + kLzBlk - 1) / kLzBlk + 1) / 2;
+    int S = 1;
+    while (S < 16 && 2 * S <= nl && (T / (2 * S)) >= half) S *= 2;
+    if (S == 1) {
+      int64_t lo[kLzCols], hi[kLzCols];
+      lz_zero(lo, hi);
+      lz_product(a, nl, b, nl, sgn, NC, lo, hi);
+      __syncthreads();
+      lz_store_cols(lo, hi, NC, sh);
+      return;
+    }
+    for (int k = t; k < NC; k += T) sh.coef[k] = 0;
     __syncthreads();
-    lz_store_cols(lo, hi, NC, sh);
+    const int Tg = T / S, grp = t / Tg, tl = t - grp * Tg;
+    const int pl = (nl + S - 1) / S, a0 = min(nl, grp * pl), na = min(nl, a0 + pl) - a0;
+    if (na > 0) {
+      const int NCs = na + nl + 1;               // this slice's columns, from column a0
+      int64_t lo[kLzCols], hi[kLzCols];
+      lz_zero(lo, hi);
+      lz_product(a + a0, na, b, nl, sgn, NCs, lo, hi, tl);
+      unsigned long long* cf = reinterpret_cast<unsigned long long*>(sh.coef + a0);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k0 = lz_block_start(q, NCs, tl);
+        if (k0 < 0) continue;
+#pragma unroll
+        for (int c = 0; c < kLzBlk; ++c) {
+          if (k0 + c < NCs) atomicAdd(cf + k0 + c, (unsigned long long)lo[q * kLzBlk + c]);
+          if (k0 + c + 1 < NCs) atomicAdd(cf + k0 + c + 1, (unsigned long long)hi[q * kLzBlk + c]);
+        }
+      }
+    }
+    __syncthreads();
     return;
   }
   int64_t* cur = dist.cols + (int64_t)(dist.k % 3) * kLzMaxNC;
