@@ -156,7 +156,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "a multi-GPU layout is not built.", file=sys.stderr)
         sys.exit(2)
 

@@ -376,7 +376,7 @@ int hmv_debug_force_tiles(int32_t x_tile, int32_t y_tile);
  * form wherever it applies (the default).  Both give the same words.      */
 int hmv_debug_force_school(int32_t form);
 /* tests only: spin limit of the dependency waits of the single-launch batch
- * driver (switched off in this build; kept for its test); 0 = default.     */
+ * driver (that driver is switched off; kept for its test); 0 = default.   */
 int hmv_debug_batch_spin_limit(int32_t spins);
 
 /* Device status of the last call that used workspace `ws`: synchronises

@@ -198,8 +198,8 @@ __device__ inline bool number_in_range(const uint64_t* wd, int W, int P) {
 // of its own.  rf: two LDS flags (every high bit equals the sign bit; the
 // number is 2^P) that thread 0 sets with range_flags_init before the
 // barrier which publishes the words; a wave holding a word that breaks a
-// test clears its flag.  After a later barrier range_flags_ok(rf) gives the
-// verdict.
+// test clears its flag.  After a later barrier range_flags_ok(rf) tells
+// whether the number is in range.
 __device__ inline void range_flags_init(uint32_t* rf) {
   if (threadIdx.x == 0) {
     rf[0] = 1u;
