@@ -30,7 +30,11 @@ def _run(H, q1, n, P, steps, algo="split_fft"):
 
 @pytest.mark.parametrize("n,P,steps,algo", [
     (8, 100, 8, "split_fft"), (16, 3322, 12, "split_fft"), (33, 1000, 20, "ntt"),
-    (24, 500, 10, "karatsuba"), (64, 3322, 16, "split_fft"), (5, 64, 5, "auto")])
+    (24, 500, 10, "karatsuba"), (64, 3322, 16, "split_fft"), (5, 64, 5, "auto"),
+    # 512 entries and more: one work-group per entry for the dot products and the
+    # updates (fewer entries split every product over several work-groups); past
+    # 1024 entries a dot-product work-group takes several entries
+    (600, 200, 3, "split_fft"), (1100, 100, 2, "split_fft")])
 def test_equals_oracle(n, P, steps, algo):
     need_gpu()
     H = fp.decode(si.uniform(2 * n - 1, P, (100, n, P)))
