@@ -829,7 +829,9 @@ __global__ void k_lz_copy(const uint64_t* src, uint64_t* dst, int64_t words, con
     dst[m] = src[m];
 }
 
-// Work-groups of the scalar kernel: up to 64, all resident at once.
+// Work-groups of the scalar kernel: up to 32, all resident at once (16 to 32
+// take the same time per step; 64 wait longer at each grid barrier of a
+// split product, 8 multiply too much each).
 hipError_t lz_scalars_grid(int* grid) {
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -838,7 +840,7 @@ hipError_t lz_scalars_grid(int* grid) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_lz_scalars,
                                                      kLzThreads, 0);
   if (e != hipSuccess) return e;
-  *grid = std::max(1, std::min(64, per_cu * cus));
+  *grid = std::max(1, std::min(32, per_cu * cus));
   return hipSuccess;
 }
 
